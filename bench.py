@@ -1,0 +1,155 @@
+"""Benchmark of the D2Q9 cascaded LBM step with consistent forcing on one GPU.
+
+Workload: the decaying Taylor-Green vortex plus a uniform body force
+(Fx, Fy) = (1e-6, 5e-7) on a periodic 4096 x 4096 lattice, u0 = 0.01,
+nu = 0.01, populations stored as FP32 deviations f_i - w_i rho0, FP32
+arithmetic.  A step is one fused collide-and-stream launch over the whole
+lattice (Eqs. 9-15).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
+algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
+oracle's throughput on the host cores for a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_LUP = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}
+KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_kernels.hip",
+                  "paper_1705_11092_amd/csrc/clbm_device.h",
+                  "paper_1705_11092_amd/csrc/clbm_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_tg4096.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, n_nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("storage") != storage:
+        return None
+    if t.get("nodes") != n_nodes:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def run_gpu(n: int, storage: str, steps: int, warmup: int):
+    import torch
+    from paper_1705_11092_amd import clbm, inputs
+
+    wl = inputs.taylor_green(n, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=steps)
+    lat = clbm.lattice_from_workload(wl, storage=storage)
+    stream = lat.stream
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    _, _, _, tot = lat.moments(fields=False)
+    lat.close()
+    return ms, wall, tot
+
+
+def cpu_baseline(n: int, budget_s: float = 12.0):
+    """The oracle on the host cores: the same 4096^2 workload, as many steps
+    as fit in about budget_s seconds after one timed probe step."""
+    import oracle
+    from paper_1705_11092_amd import inputs
+
+    wl = inputs.taylor_green(n, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=1)
+    fx, fy = oracle.force_field(wl.force_kind, wl.force_params, n, n)
+    f = oracle.init(wl.rho, wl.ux, wl.uy, fx, fy)
+    t = time.perf_counter()
+    f = oracle.step(f, fx, fy, wl.s)
+    one = time.perf_counter() - t
+    k = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    t = time.perf_counter()
+    oracle.run(f, fx, fy, wl.s, k)
+    dt = time.perf_counter() - t
+    return {"value": round(n * n * k / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{k} steps of the {n}x{n} FP64 oracle on the same Taylor-Green workload"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
+              "multi-GPU path; the lattice would be split into y-slabs with one halo "
+              "exchange per step.", file=sys.stderr)
+        sys.exit(2)
+
+    ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup)
+    nodes = args.n * args.n
+    ms_step = ms / args.steps
+    mlups = nodes / (ms_step / 1e3) / 1e6
+    bpl = BYTES_PER_LUP[args.storage]
+    achieved = bpl * nodes / (ms_step / 1e3) / 1e9
+    traffic = measured_traffic(args.storage, nodes)
+    line = {
+        "metric": "MLUPS (D2Q9 CLBM step, consistent forcing)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"taylor_green_{args.n}x{args.n}_uniform_force",
+                   "storage": f"{args.storage} deviations f_i - w_i rho0",
+                   "nodes": nodes, "bytes_per_lup": bpl, "boundary": "periodic",
+                   "u0": 0.01, "nu": 0.01, "F": [1e-6, 5e-7]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "wall_s": round(wall, 4),
+        "mass_total": tot[0],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

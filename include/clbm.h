@@ -1,0 +1,222 @@
+/*
+ * clbm.h -- C-ABI of the D2Q9 cascaded lattice Boltzmann library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is the cascaded (central-moment) lattice Boltzmann method with
+ * the consistent forcing scheme of Fei & Luo, "Consistent forcing scheme in
+ * the cascaded lattice Boltzmann method":
+ *   - D2Q9 velocities e_i in the order of Eq. (1), c = 1, cs^2 = 1/3;
+ *   - raw moments T = M f (Eqs. 2-5), central moments T~ = N(u) T (Eq. 6);
+ *   - collision T~* = (I - S) T~ + S T~eq + (I - S/2) C (Eq. 12, first
+ *     line), with T~eq of Eq. (8) and the force moments C of Eq. (14) read
+ *     as C = [0, Fx, Fy, 0, 0, 0, cs^2 Fy, cs^2 Fx, 0];
+ *   - back-transform f* = M^-1 N^-1(u) T~* (Eq. 9) and streaming
+ *     f_i(x + e_i, t + 1) = f_i*(x, t) (Eq. 10);
+ *   - density and forced velocity rho = sum f, rho u = sum f e + F/2
+ *     (Eqs. 11 and 15), which is also the u used in N and N^-1;
+ *   - x periodic; y periodic or closed by half-way bounce-back walls half a
+ *     link outside rows 0 and ny-1 (Sec. IV A).
+ *
+ * Conventions shared by every call:
+ *   - All functions return CLBM_OK (0) on success and a negative CLBM_E*
+ *     code on failure; clbm_last_error() then holds a message for the
+ *     calling thread.  No C++ exception crosses this interface.
+ *   - Per-node fields are FP64, [ny][nx] row-major (x fastest).
+ *     Populations exchanged with the caller are FP64 [9][ny][nx] in the
+ *     direction order of Eq. (1), and are the pre-collision f(x, t).
+ *   - Device pointers are HIP device memory on the current device.  The
+ *     caller owns every buffer it passes (populations, fields); the library
+ *     never frees them.  The library owns only its handle, a small FP64
+ *     reduction scratch, the force tables it builds and its hipGraphs.
+ *   - Work is enqueued on the stream given at creation and is asynchronous,
+ *     except where a call says it synchronises.
+ *   - A handle may be used from one host thread at a time.
+ */
+#ifndef CLBM_H
+#define CLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define CLBM_OK 0
+#define CLBM_EINVAL (-1)     /* bad argument: size, rate, null pointer ...   */
+#define CLBM_EHIP (-2)       /* a HIP runtime call failed                    */
+#define CLBM_ESTATE (-3)     /* wrong call order (e.g. step before init)     */
+#define CLBM_ENONFINITE (-4) /* the FP64 totals are NaN or Inf               */
+
+/* ---- enumerations ------------------------------------------------------ */
+
+/* Storage of the populations.  Every type stores the deviation
+ * f_i - w_i rho0 from the rest equilibrium w_i rho0 (w = 4/9, 1/9 x4,
+ * 1/36 x4).  CLBM_F64 computes in FP64; the others compute in FP32. */
+typedef enum {
+    CLBM_F64 = 0,
+    CLBM_F32 = 1,
+    CLBM_F16 = 2,  /* IEEE binary16, round to nearest even */
+    CLBM_BF16 = 3  /* bfloat16, round to nearest even      */
+} clbm_storage;
+
+/* Boundary in y (x is always periodic), Sec. IV A. */
+typedef enum { CLBM_Y_PERIODIC = 0, CLBM_Y_BOUNCEBACK = 1 } clbm_bc_y;
+
+/* Body force density F(x). */
+typedef enum {
+    CLBM_FORCE_NONE = 0,       /* F = 0                                      */
+    CLBM_FORCE_CONST = 1,      /* params = {Fx, Fy}                          */
+    CLBM_FORCE_KOLMOGOROV = 2, /* params = {A, k}: Fx = A sin(2 pi k y/ny)   */
+    CLBM_FORCE_FIELD = 3       /* fx, fy: device FP64 [ny][nx], copied in    */
+} clbm_force_kind;
+
+/* Forcing scheme.  CONSISTENT is the paper's (Eq. 12).  GUO_LBL is the
+ * Lycett-Brown & Luo scheme with Guo's term (Eq. 21), kept for the paper's
+ * comparisons; it needs s1 = s2 to conserve momentum (Remark 5). */
+typedef enum { CLBM_SCHEME_CONSISTENT = 0, CLBM_SCHEME_GUO_LBL = 1 } clbm_scheme;
+
+/* ---- single lattice ---------------------------------------------------- */
+
+typedef struct clbm_handle clbm_handle;
+
+typedef struct {
+    int32_t nx, ny;   /* nodes, 1 <= nx, ny; nx * ny <= 2^31 - 1              */
+    int32_t bc_y;     /* clbm_bc_y                                             */
+    int32_t storage;  /* clbm_storage                                          */
+    int32_t scheme;   /* clbm_scheme                                           */
+    int32_t reserved; /* must be 0                                             */
+    /* S = diag(s0, s1, s1, sb, s2, s2, s3, s3, s4) (Sec. II A); each rate in
+     * (0, 2).  s2 = 1/(3 nu + 0.5), sb = 1/(3 xi + 0.5). */
+    double s0, s1, sb, s2, s3, s4;
+    double rho0;      /* reference density of the deviation storage, > 0     */
+    void *pop_a;      /* device buffer of clbm_buffer_bytes(nx, ny, storage) */
+    void *pop_b;      /* second buffer of the same size (ping-pong)          */
+    void *stream;     /* hipStream_t for all work of this handle; NULL = the
+                         null stream                                         */
+} clbm_config;
+
+/* Bytes each of pop_a and pop_b must hold for this lattice and storage.  The
+ * layout inside is the library's (9 padded planes); use
+ * clbm_get_populations / clbm_set_populations to read or write the state.
+ * Returns 0 for invalid arguments. */
+size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage);
+
+/* Validate cfg and create a handle.  Allocates the FP64 reduction scratch
+ * (a few KB of device memory) and pinned host memory for the totals.
+ * Errors: CLBM_EINVAL (any field out of range, null buffers, pop_a ==
+ * pop_b), CLBM_EHIP. */
+int clbm_create(const clbm_config *cfg, clbm_handle **out);
+
+/* Wait for the handle's stream, release the handle and what it owns.
+ * Accepts NULL. */
+int clbm_destroy(clbm_handle *h);
+
+/* Set the body force F(x) of Eqs. (12)-(15).  CONST and KOLMOGOROV read
+ * params[2] (host); FIELD copies the caller's device arrays fx, fy (FP64
+ * [ny][nx]) into a library-owned device buffer in the arithmetic type, so
+ * the caller may free them once the stream has passed this call.  A new
+ * force applies from the next step; clbm_init uses the force set before it.
+ * Errors: CLBM_EINVAL (unknown kind, missing params or arrays, non-finite
+ * values), CLBM_EHIP. */
+int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const double *fx,
+                   const double *fy);
+
+/* Start state f(x, 0) at every node: the pre-collision populations whose
+ * central moments about u are [rho, -Fx/2, -Fy/2, 2 rho cs^2, 0, 0, 0, 0,
+ * rho cs^4], so that Eq. (15) returns exactly the given (rho, u) under the
+ * current force.  rho, ux, uy are device FP64 [ny][nx]; NULL rho means
+ * rho0 everywhere and NULL ux / uy mean zero.  Resets the step count.
+ * Errors: CLBM_EINVAL, CLBM_EHIP. */
+int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double *uy);
+
+/* Advance nsteps >= 0 time steps: per node the collision of Eq. (12) and
+ * the back-transform of Eq. (9), then streaming (Eq. 10), fused in one
+ * kernel launch per step (pull form: each node gathers its pre-collision
+ * populations from its neighbours' post-collision ones).  Long runs replay
+ * a captured hipGraph.  Errors: CLBM_ESTATE before clbm_init or
+ * clbm_set_populations, CLBM_EINVAL (nsteps < 0), CLBM_EHIP. */
+int clbm_step(clbm_handle *h, int64_t nsteps);
+
+/* Steps taken since the last clbm_init / clbm_set_populations. */
+int64_t clbm_step_count(const clbm_handle *h);
+
+/* Density (Eq. 11) and forced velocity (Eq. 15) of the current state
+ * f(x, t): rho, ux, uy are device FP64 [ny][nx] outputs, each may be NULL.
+ * totals, if not NULL, is host memory for {sum rho, sum rho ux,
+ * sum rho uy} over all nodes, reduced in FP64 on the GPU in a fixed order;
+ * then the call waits for the stream and returns CLBM_ENONFINITE if a total
+ * is NaN or Inf.  Errors: CLBM_ESTATE, CLBM_EHIP, CLBM_ENONFINITE. */
+int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *totals);
+
+/* FP64 error norms on the GPU against reference velocity fields ux_ref,
+ * uy_ref (device FP64 [ny][nx]): out[0] = sum |u - u_ref|^2 and out[1] =
+ * sum |u_ref|^2 over both components and all nodes (host), so that
+ * E2 = sqrt(out[0] / out[1]) as in Eq. (24).  Synchronises.
+ * Errors: CLBM_EINVAL, CLBM_ESTATE, CLBM_EHIP. */
+int clbm_error_norms(clbm_handle *h, const double *ux_ref, const double *uy_ref, double *out);
+
+/* Copy the current pre-collision state f(x, t) out to f (device FP64
+ * [9][ny][nx], absolute populations, not deviations). */
+int clbm_get_populations(clbm_handle *h, double *f);
+
+/* Replace the state by f (device FP64 [9][ny][nx] pre-collision
+ * populations), rounded to the storage type.  Resets the step count. */
+int clbm_set_populations(clbm_handle *h, const double *f);
+
+/* Steps per captured hipGraph replay in clbm_step; 0 launches every step
+ * directly.  Default 64. */
+int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *clbm_last_error(void);
+
+/* Remark 4: the s3 that removes the slip of half-way bounce-back,
+ * (16 - 8 s2)/(8 - s2). */
+double clbm_nonslip_s3(double s2);
+
+/* Sec. II A: s2 = 1/(3 nu + 0.5). */
+double clbm_s_from_nu(double nu);
+
+/* ---- batches of lattices ----------------------------------------------- */
+
+/* A batch advances many independent lattices (any sizes, storages, forces,
+ * rates and y boundaries) with one persistent kernel launch per time step.
+ * Each node is updated by exactly the arithmetic of clbm_step, so a
+ * lattice's result is bitwise the same alone and in any batch. */
+typedef struct clbm_batch clbm_batch;
+
+/* Build a batch over count >= 1 existing handles (not owned; they must
+ * outlive the batch, and while the batch exists they must be stepped only
+ * through it).  All work goes to stream.  Allocates the device tile list
+ * and lattice table.  Errors: CLBM_EINVAL (duplicates, NULLs), CLBM_EHIP. */
+int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream,
+                      clbm_batch **out);
+
+/* Advance every lattice of the batch nsteps time steps. */
+int clbm_batch_step(clbm_batch *b, int64_t nsteps);
+
+/* Advance lattice j by nsteps[j] >= 0 steps (host array of count entries):
+ * max(nsteps) launches, each skipping the lattices already done. */
+int clbm_batch_step_each(clbm_batch *b, const int64_t *nsteps);
+
+/* Time the kernel variants of the batch on its own lattices and keep the
+ * fastest (results do not depend on the variant).  With cache_path set,
+ * look the choice up first and record it after, keyed by architecture and
+ * batch shape.  *chosen (optional) receives the variant index. */
+int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen);
+
+/* Number of kernel variants, and the one in use (settable). */
+int32_t clbm_batch_variant_count(void);
+int clbm_batch_set_variant(clbm_batch *b, int32_t variant);
+int32_t clbm_batch_get_variant(const clbm_batch *b);
+
+/* Release the batch (not its lattices).  Accepts NULL. */
+int clbm_batch_destroy(clbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLBM_H */

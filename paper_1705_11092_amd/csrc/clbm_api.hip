@@ -1,0 +1,774 @@
+// clbm_api.hip -- the C-ABI of include/clbm.h: handles, argument checks,
+// graph replay of step sequences, batches and the batch autotuner.
+#include "clbm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "clbm_device.h"
+#include "clbm_internal.h"
+
+using clbm::LatDesc;
+using clbm::Tile;
+
+// Extra elements between population planes (skews the nine streams across
+// HBM channels; 0 keeps planes back to back).
+#ifndef CLBM_PLANE_PAD_ELEMS
+#define CLBM_PLANE_PAD_ELEMS 0
+#endif
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return CLBM_EHIP;
+}
+
+#define HIPCHK(expr)                                                 \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);            \
+    } while (0)
+
+int elem_bytes(int storage)
+{
+    switch (storage) {
+    case CLBM_F64: return 8;
+    case CLBM_F32: return 4;
+    case CLBM_F16:
+    case CLBM_BF16: return 2;
+    default: return 0;
+    }
+}
+
+int64_t pitch_of(int nx) { return ((int64_t)nx + clbm::kRowAlign - 1) / clbm::kRowAlign * clbm::kRowAlign; }
+
+// Planes start on 256-byte boundaries (64 elements covers every type).
+int64_t plane_of(int nx, int ny)
+{
+    const int64_t raw = pitch_of(nx) * ny;
+    return (raw + 63) / 64 * 64 + CLBM_PLANE_PAD_ELEMS;
+}
+
+bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
+
+// Default nodes per thread of the single-lattice step: 16-byte vectors.
+int default_vec(int storage)
+{
+    switch (storage) {
+    case CLBM_F64: return 2;
+    case CLBM_F32: return 4;
+    default: return 8;
+    }
+}
+
+// Check that [p, p + bytes) lies inside one HIP device allocation.
+int check_device_range(const void *p, size_t bytes, const char *name)
+{
+    if (!p) return fail(CLBM_EINVAL, std::string(name) + " is NULL");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CLBM_EINVAL, std::string(name) + " is not HIP memory");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(CLBM_EINVAL, std::string(name) + " is not device memory");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) == hipSuccess && base) {
+        const char *b = static_cast<const char *>(base);
+        const char *q = static_cast<const char *>(p);
+        if (q < b || q + bytes > b + size)
+            return fail(CLBM_EINVAL, std::string(name) + " is smaller than required");
+    } else {
+        (void)hipGetLastError();
+    }
+    return CLBM_OK;
+}
+
+}  // namespace
+
+// ---- handle ----------------------------------------------------------------
+
+struct clbm_handle {
+    clbm_config cfg;
+    LatDesc d;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream used only to capture graphs
+    int parity = 0;             // buffer holding the current state
+    int64_t steps = 0;
+    bool ready = false;
+    void *force_buf = nullptr;
+    double *partials = nullptr;  // per-block FP64 partial sums
+    double *d_out = nullptr;     // reduced totals on the device
+    double *h_out = nullptr;     // pinned copy of the totals
+    int vec = 4;
+    int graph_steps = 64;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void drop_graphs(clbm_handle *h)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (h->graph[p]) (void)hipGraphExecDestroy(h->graph[p]);
+        h->graph[p] = nullptr;
+    }
+}
+
+int build_graph(clbm_handle *h, int parity)
+{
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
+        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, h->cap);
+    hipError_t ce = hipStreamEndCapture(h->cap, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "launch_step (capture)");
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    return CLBM_OK;
+}
+
+int need_ready(const clbm_handle *h)
+{
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (!h->ready) return fail(CLBM_ESTATE, "lattice has no state yet: call clbm_init or clbm_set_populations");
+    return CLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage)
+{
+    const int eb = elem_bytes(storage);
+    if (nx < 1 || ny < 1 || eb == 0) return 0;
+    if (pitch_of(nx) * (int64_t)ny > (int64_t)INT32_MAX) return 0;
+    return (size_t)(9 * plane_of(nx, ny) * eb);
+}
+
+int clbm_create(const clbm_config *cfg, clbm_handle **out)
+{
+    g_err.clear();
+    if (!cfg || !out) return fail(CLBM_EINVAL, "cfg and out must not be NULL");
+    *out = nullptr;
+    if (cfg->nx < 1 || cfg->ny < 1) return fail(CLBM_EINVAL, "nx and ny must be >= 1");
+    if (pitch_of(cfg->nx) * (int64_t)cfg->ny > (int64_t)INT32_MAX)
+        return fail(CLBM_EINVAL, "lattice too large (nx * ny must stay below 2^31)");
+    if (cfg->bc_y != CLBM_Y_PERIODIC && cfg->bc_y != CLBM_Y_BOUNCEBACK)
+        return fail(CLBM_EINVAL, "bc_y must be CLBM_Y_PERIODIC or CLBM_Y_BOUNCEBACK");
+    if (elem_bytes(cfg->storage) == 0) return fail(CLBM_EINVAL, "unknown storage");
+    if (cfg->scheme != CLBM_SCHEME_CONSISTENT && cfg->scheme != CLBM_SCHEME_GUO_LBL)
+        return fail(CLBM_EINVAL, "unknown scheme");
+    if (cfg->reserved != 0) return fail(CLBM_EINVAL, "reserved must be 0");
+    const double rates[6] = {cfg->s0, cfg->s1, cfg->sb, cfg->s2, cfg->s3, cfg->s4};
+    for (double s : rates)
+        if (!rate_ok(s)) return fail(CLBM_EINVAL, "every relaxation rate must lie in (0, 2]");
+    if (!std::isfinite(cfg->rho0) || cfg->rho0 <= 0.0) return fail(CLBM_EINVAL, "rho0 must be > 0");
+    if (cfg->pop_a == cfg->pop_b) return fail(CLBM_EINVAL, "pop_a and pop_b must differ");
+    const size_t need = clbm_buffer_bytes(cfg->nx, cfg->ny, cfg->storage);
+    int rc = check_device_range(cfg->pop_a, need, "pop_a");
+    if (rc) return rc;
+    rc = check_device_range(cfg->pop_b, need, "pop_b");
+    if (rc) return rc;
+
+    clbm_handle *h = new clbm_handle();
+    h->cfg = *cfg;
+    h->stream = static_cast<hipStream_t>(cfg->stream);
+    LatDesc &d = h->d;
+    std::memset(&d, 0, sizeof d);
+    d.buf[0] = cfg->pop_a;
+    d.buf[1] = cfg->pop_b;
+    d.plane = plane_of(cfg->nx, cfg->ny);
+    d.nx = cfg->nx;
+    d.ny = cfg->ny;
+    d.pitch = (int32_t)pitch_of(cfg->nx);
+    d.bc_y = cfg->bc_y;
+    d.storage = cfg->storage;
+    d.force_mode = clbm::FM_CONST;
+    d.scheme = cfg->scheme;
+    d.rho0 = cfg->rho0;
+    d.om1 = 1.0 - cfg->s1;
+    d.omb = 1.0 - cfg->sb;
+    d.om2 = 1.0 - cfg->s2;
+    d.om3 = 1.0 - cfg->s3;
+    d.om4 = 1.0 - cfg->s4;
+    d.h3 = 1.0 - 0.5 * cfg->s3;
+    d.h2 = 1.0 - 0.5 * cfg->s2;
+    h->vec = default_vec(cfg->storage);
+
+    const int nb = clbm::moments_blocks((int64_t)cfg->nx * cfg->ny);
+    hipError_t e = hipMalloc(&h->partials, sizeof(double) * (3 * (size_t)nb + 3));
+    if (e == hipSuccess) h->d_out = h->partials + 3 * (size_t)nb;
+    if (e == hipSuccess) e = hipHostMalloc(&h->h_out, 3 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        clbm_destroy(h);
+        return hip_fail(e, "clbm_create allocations");
+    }
+    *out = h;
+    return CLBM_OK;
+}
+
+int clbm_destroy(clbm_handle *h)
+{
+    if (!h) return CLBM_OK;
+    if (h->stream || h->ready) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->force_buf) (void)hipFree(h->force_buf);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    delete h;
+    return CLBM_OK;
+}
+
+int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const double *fx,
+                   const double *fy)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    LatDesc &d = h->d;
+    const size_t rb = d.storage == CLBM_F64 ? 8 : 4;
+    const int64_t n = (int64_t)d.nx * d.ny;
+    switch (kind) {
+    case CLBM_FORCE_NONE:
+    case CLBM_FORCE_CONST: {
+        double Fx = 0.0, Fy = 0.0;
+        if (kind == CLBM_FORCE_CONST) {
+            if (!params) return fail(CLBM_EINVAL, "CONST force needs params {Fx, Fy}");
+            Fx = params[0];
+            Fy = params[1];
+            if (!std::isfinite(Fx) || !std::isfinite(Fy)) return fail(CLBM_EINVAL, "force is not finite");
+        }
+        d.force_mode = clbm::FM_CONST;
+        d.Fx = Fx;
+        d.Fy = Fy;
+        break;
+    }
+    case CLBM_FORCE_KOLMOGOROV:
+    case CLBM_FORCE_FIELD: {
+        const size_t bytes = kind == CLBM_FORCE_KOLMOGOROV ? rb * (size_t)d.ny : 2 * rb * (size_t)n;
+        if (kind == CLBM_FORCE_KOLMOGOROV) {
+            if (!params) return fail(CLBM_EINVAL, "KOLMOGOROV force needs params {A, k}");
+            if (!std::isfinite(params[0]) || !std::isfinite(params[1]))
+                return fail(CLBM_EINVAL, "force parameters are not finite");
+        } else {
+            int rc = check_device_range(fx, sizeof(double) * n, "fx");
+            if (rc) return rc;
+            rc = check_device_range(fy, sizeof(double) * n, "fy");
+            if (rc) return rc;
+        }
+        // The old table may still be read by queued steps.
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->force_buf) HIPCHK(hipFree(h->force_buf));
+        h->force_buf = nullptr;
+        HIPCHK(hipMalloc(&h->force_buf, bytes));
+        if (kind == CLBM_FORCE_KOLMOGOROV) {
+            d.force_mode = clbm::FM_ROW;
+            HIPCHK(clbm::launch_force_table(d, h->force_buf, params[0], params[1], h->stream));
+        } else {
+            d.force_mode = clbm::FM_FIELD;
+            HIPCHK(clbm::launch_force_field(d, h->force_buf, fx, fy, h->stream));
+        }
+        d.force = h->force_buf;
+        d.Fx = d.Fy = 0.0;
+        break;
+    }
+    default:
+        return fail(CLBM_EINVAL, "unknown force kind");
+    }
+    drop_graphs(h);
+    return CLBM_OK;
+}
+
+int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double *uy)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    const size_t fb = sizeof(double) * (size_t)h->d.nx * h->d.ny;
+    int rc;
+    if (rho && (rc = check_device_range(rho, fb, "rho"))) return rc;
+    if (ux && (rc = check_device_range(ux, fb, "ux"))) return rc;
+    if (uy && (rc = check_device_range(uy, fb, "uy"))) return rc;
+    HIPCHK(clbm::launch_init(h->d, 0, rho, ux, uy, h->stream));
+    h->parity = 0;
+    h->steps = 0;
+    h->ready = true;
+    return CLBM_OK;
+}
+
+int clbm_step(clbm_handle *h, int64_t nsteps)
+{
+    g_err.clear();
+    int rc = need_ready(h);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (h->graph_steps > 0 && left >= h->graph_steps) {
+            if (!h->graph[h->parity] && (rc = build_graph(h, h->parity))) return rc;
+            HIPCHK(hipGraphLaunch(h->graph[h->parity], h->stream));
+            left -= h->graph_steps;  // even, so the parity is unchanged
+        } else {
+            HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, h->stream));
+            h->parity ^= 1;
+            left -= 1;
+        }
+    }
+    h->steps += nsteps;
+    return CLBM_OK;
+}
+
+int64_t clbm_step_count(const clbm_handle *h) { return h ? h->steps : -1; }
+
+int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *totals)
+{
+    g_err.clear();
+    int rc = need_ready(h);
+    if (rc) return rc;
+    const size_t fb = sizeof(double) * (size_t)h->d.nx * h->d.ny;
+    if (rho && (rc = check_device_range(rho, fb, "rho"))) return rc;
+    if (ux && (rc = check_device_range(ux, fb, "ux"))) return rc;
+    if (uy && (rc = check_device_range(uy, fb, "uy"))) return rc;
+    int nb = 0;
+    HIPCHK(clbm::launch_moments(h->d, h->parity, rho, ux, uy, nullptr, nullptr, h->partials, &nb,
+                                h->stream));
+    if (!totals) return CLBM_OK;
+    HIPCHK(clbm::launch_reduce(h->partials, nb, 3, h->d_out, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    totals[0] = (double)h->d.nx * h->d.ny * h->d.rho0 + h->h_out[0];
+    totals[1] = h->h_out[1];
+    totals[2] = h->h_out[2];
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(totals[c])) return fail(CLBM_ENONFINITE, "mass or momentum is not finite");
+    return CLBM_OK;
+}
+
+int clbm_error_norms(clbm_handle *h, const double *ux_ref, const double *uy_ref, double *out)
+{
+    g_err.clear();
+    int rc = need_ready(h);
+    if (rc) return rc;
+    if (!out) return fail(CLBM_EINVAL, "out is NULL");
+    const size_t fb = sizeof(double) * (size_t)h->d.nx * h->d.ny;
+    if ((rc = check_device_range(ux_ref, fb, "ux_ref"))) return rc;
+    if ((rc = check_device_range(uy_ref, fb, "uy_ref"))) return rc;
+    int nb = 0;
+    HIPCHK(clbm::launch_moments(h->d, h->parity, nullptr, nullptr, nullptr, ux_ref, uy_ref,
+                                h->partials, &nb, h->stream));
+    HIPCHK(clbm::launch_reduce(h->partials, nb, 2, h->d_out, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    out[0] = h->h_out[0];
+    out[1] = h->h_out[1];
+    return CLBM_OK;
+}
+
+int clbm_get_populations(clbm_handle *h, double *f)
+{
+    g_err.clear();
+    int rc = need_ready(h);
+    if (rc) return rc;
+    if ((rc = check_device_range(f, 9 * sizeof(double) * (size_t)h->d.nx * h->d.ny, "f"))) return rc;
+    HIPCHK(clbm::launch_get_populations(h->d, h->parity, f, h->stream));
+    return CLBM_OK;
+}
+
+int clbm_set_populations(clbm_handle *h, const double *f)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    int rc = check_device_range(f, 9 * sizeof(double) * (size_t)h->d.nx * h->d.ny, "f");
+    if (rc) return rc;
+    HIPCHK(clbm::launch_set_populations(h->d, 0, f, h->stream));
+    h->parity = 0;
+    h->steps = 0;
+    h->ready = true;
+    return CLBM_OK;
+}
+
+int clbm_set_graph_steps(clbm_handle *h, int32_t steps)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (steps < 0 || steps > 4096) return fail(CLBM_EINVAL, "graph steps must lie in [0, 4096]");
+    drop_graphs(h);
+    h->graph_steps = (steps + 1) / 2 * 2;
+    return CLBM_OK;
+}
+
+const char *clbm_last_error(void) { return g_err.c_str(); }
+
+double clbm_nonslip_s3(double s2) { return (16.0 - 8.0 * s2) / (8.0 - s2); }
+
+double clbm_s_from_nu(double nu) { return 1.0 / (3.0 * nu + 0.5); }
+
+}  // extern "C"
+
+// ---- batches ---------------------------------------------------------------
+
+namespace {
+
+// Kernel variants of a batch: bytes each thread loads per direction (nodes
+// per thread = bytes / element size, clamped to the compiled set) and
+// persistent blocks per compute unit.
+struct Variant {
+    int vec_bytes;
+    int blocks_per_cu;
+};
+const Variant kVariants[] = {
+    {16, 8}, {16, 4}, {16, 16}, {8, 8}, {8, 4}, {8, 16}, {4, 8}, {4, 4}, {4, 16},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int vec_for(int storage, int vec_bytes)
+{
+    switch (storage) {
+    case CLBM_F64: return vec_bytes >= 16 ? 2 : 1;
+    case CLBM_F32: return vec_bytes >= 16 ? 4 : (vec_bytes >= 8 ? 2 : 1);
+    default: return vec_bytes >= 16 ? 8 : (vec_bytes >= 8 ? 4 : 2);
+    }
+}
+
+}  // namespace
+
+struct clbm_batch {
+    std::vector<clbm_handle *> lats;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    LatDesc *d_lats = nullptr;  // device lattice table
+    LatDesc *h_lats = nullptr;  // pinned staging of the table
+    hipEvent_t staged = nullptr;  // last upload from h_lats
+    bool staged_pending = false;
+    Tile *d_tiles = nullptr;
+    struct Group {
+        int storage, vec;
+        int64_t first, count;
+    };
+    std::vector<Group> groups;
+    int variant = 0;
+    int cus = 256;
+    int chunk = 32;  // launches per captured graph
+    hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+void batch_drop_graph(clbm_batch *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+}
+
+// Tile lists of the current variant, grouped by storage type.
+int batch_build_tiles(clbm_batch *b)
+{
+    std::vector<Tile> tiles;
+    b->groups.clear();
+    for (int st = 0; st < 4; ++st) {
+        const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
+        const int64_t first = (int64_t)tiles.size();
+        for (size_t j = 0; j < b->lats.size(); ++j) {
+            const LatDesc &d = b->lats[j]->d;
+            if (d.storage != st) continue;
+            int32_t tpr, rows, segs;
+            int64_t nt;
+            clbm::tile_geometry(d.nx, d.ny, vec, &tpr, &rows, &segs, &nt);
+            for (int64_t t = 0; t < nt; ++t) tiles.push_back(Tile{(int32_t)j, (int32_t)t});
+        }
+        if ((int64_t)tiles.size() > first)
+            b->groups.push_back({st, vec, first, (int64_t)tiles.size() - first});
+    }
+    if (b->d_tiles) {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        HIPCHK(hipFree(b->d_tiles));
+        b->d_tiles = nullptr;
+    }
+    HIPCHK(hipMalloc(&b->d_tiles, sizeof(Tile) * tiles.size()));
+    HIPCHK(hipMemcpy(b->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
+    batch_drop_graph(b);
+    return CLBM_OK;
+}
+
+// Copy the lattices' descriptors, with their current parity and the steps
+// each takes in this call, to the device table.
+int batch_upload(clbm_batch *b, const int64_t *nsteps)
+{
+    if (b->staged_pending) HIPCHK(hipEventSynchronize(b->staged));
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+        const clbm_handle *h = b->lats[j];
+        LatDesc d = h->d;
+        const int vec = vec_for(d.storage, kVariants[b->variant].vec_bytes);
+        int64_t nt;
+        clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.rows, &d.segs, &nt);
+        d.vec = vec;
+        d.parity = h->parity;
+        d.steps = (int32_t)nsteps[j];
+        b->h_lats[j] = d;
+    }
+    HIPCHK(hipMemcpyAsync(b->d_lats, b->h_lats, sizeof(LatDesc) * b->lats.size(),
+                          hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipEventRecord(b->staged, b->stream));
+    b->staged_pending = true;
+    return CLBM_OK;
+}
+
+int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
+{
+    const int grid = b->cus * kVariants[b->variant].blocks_per_cu;
+    for (const auto &g : b->groups) {
+        const int gg = (int)std::min<int64_t>(grid, g.count);
+        HIPCHK(clbm::launch_batch(b->d_lats, b->d_tiles + g.first, g.count, g.storage, g.vec, gg,
+                                  substep, s));
+    }
+    return CLBM_OK;
+}
+
+int batch_build_graph(clbm_batch *b)
+{
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = CLBM_OK;
+    for (int k = 0; k < b->chunk && rc == CLBM_OK; ++k) rc = batch_launch_substep(b, k, b->cap);
+    hipError_t le = rc == CLBM_OK
+                        ? clbm::launch_batch_advance(b->d_lats, (int)b->lats.size(), b->chunk, b->cap)
+                        : hipSuccess;
+    hipError_t ce = hipStreamEndCapture(b->cap, &g);
+    if (rc != CLBM_OK || le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != CLBM_OK ? rc : hip_fail(le, "launch_batch_advance (capture)");
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    return CLBM_OK;
+}
+
+int batch_run(clbm_batch *b, const int64_t *nsteps)
+{
+    int64_t maxn = 0;
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+        if (nsteps[j] < 0) return fail(CLBM_EINVAL, "step counts must be >= 0");
+        if (nsteps[j] > INT32_MAX) return fail(CLBM_EINVAL, "step count too large for one call");
+        maxn = std::max(maxn, nsteps[j]);
+    }
+    for (auto *h : b->lats)
+        if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
+    if (maxn == 0) return CLBM_OK;
+    int rc = batch_upload(b, nsteps);
+    if (rc) return rc;
+    int64_t left = maxn;
+    while (left >= b->chunk) {
+        if (!b->graph && (rc = batch_build_graph(b))) return rc;
+        HIPCHK(hipGraphLaunch(b->graph, b->stream));
+        left -= b->chunk;
+    }
+    if (left > 0) {
+        for (int k = 0; k < left; ++k)
+            if ((rc = batch_launch_substep(b, k, b->stream))) return rc;
+        HIPCHK(clbm::launch_batch_advance(b->d_lats, (int)b->lats.size(), (int)left, b->stream));
+    }
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+        b->lats[j]->parity = (int)((b->lats[j]->parity + nsteps[j]) & 1);
+        b->lats[j]->steps += nsteps[j];
+    }
+    return CLBM_OK;
+}
+
+std::string batch_signature(const clbm_batch *b)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    int64_t nodes[4] = {0, 0, 0, 0}, counts[4] = {0, 0, 0, 0};
+    for (auto *h : b->lats) {
+        nodes[h->d.storage] += (int64_t)h->d.nx * h->d.ny;
+        counts[h->d.storage] += 1;
+    }
+    std::ostringstream os;
+    os << arch;
+    for (int st = 0; st < 4; ++st) {
+        // Shape class: lattice count and log2 of the node total per storage.
+        int lg = 0;
+        while (nodes[st] >> (lg + 1)) ++lg;
+        os << "|s" << st << ":n" << counts[st] << ":l" << (nodes[st] ? lg : -1);
+    }
+    return os.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream, clbm_batch **out)
+{
+    g_err.clear();
+    if (!lattices || !out || count < 1) return fail(CLBM_EINVAL, "need count >= 1 lattices and out");
+    *out = nullptr;
+    std::vector<clbm_handle *> v(lattices, lattices + count);
+    for (int j = 0; j < count; ++j) {
+        if (!v[j]) return fail(CLBM_EINVAL, "NULL lattice in batch");
+        for (int k = 0; k < j; ++k)
+            if (v[k] == v[j]) return fail(CLBM_EINVAL, "a lattice appears twice in the batch");
+    }
+    clbm_batch *b = new clbm_batch();
+    b->lats = v;
+    b->stream = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (b->cus < 1) b->cus = 256;
+    hipError_t e = hipMalloc(&b->d_lats, sizeof(LatDesc) * count);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_lats, sizeof(LatDesc) * count, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        clbm_batch_destroy(b);
+        return hip_fail(e, "clbm_batch_create allocations");
+    }
+    int rc = batch_build_tiles(b);
+    if (rc) {
+        clbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return CLBM_OK;
+}
+
+int clbm_batch_step(clbm_batch *b, int64_t nsteps)
+{
+    g_err.clear();
+    if (!b) return fail(CLBM_EINVAL, "batch is NULL");
+    std::vector<int64_t> n(b->lats.size(), nsteps);
+    return batch_run(b, n.data());
+}
+
+int clbm_batch_step_each(clbm_batch *b, const int64_t *nsteps)
+{
+    g_err.clear();
+    if (!b || !nsteps) return fail(CLBM_EINVAL, "batch and nsteps must not be NULL");
+    return batch_run(b, nsteps);
+}
+
+int32_t clbm_batch_variant_count(void) { return kNumVariants; }
+
+int clbm_batch_set_variant(clbm_batch *b, int32_t variant)
+{
+    g_err.clear();
+    if (!b) return fail(CLBM_EINVAL, "batch is NULL");
+    if (variant < 0 || variant >= kNumVariants) return fail(CLBM_EINVAL, "variant out of range");
+    if (variant == b->variant) return CLBM_OK;
+    b->variant = variant;
+    return batch_build_tiles(b);
+}
+
+int32_t clbm_batch_get_variant(const clbm_batch *b) { return b ? b->variant : -1; }
+
+int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
+{
+    g_err.clear();
+    if (!b) return fail(CLBM_EINVAL, "batch is NULL");
+    for (auto *h : b->lats)
+        if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
+    const std::string sig = batch_signature(b);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string key;
+        int v;
+        while (in >> key >> v) {
+            if (key == sig && v >= 0 && v < kNumVariants) {
+                int rc = clbm_batch_set_variant(b, v);
+                if (!rc && chosen) *chosen = v;
+                return rc;
+            }
+        }
+    }
+    // Time one step of every lattice per variant.  The timed launches read
+    // the current state and write the other buffer without advancing the
+    // lattices, so the state is untouched (the next real step overwrites
+    // that buffer).
+    std::vector<int64_t> ones(b->lats.size(), 1);
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    int best = b->variant;
+    float best_ms = 1e30f;
+    int rc = CLBM_OK;
+    for (int v = 0; v < kNumVariants && rc == CLBM_OK; ++v) {
+        if ((rc = clbm_batch_set_variant(b, v))) break;
+        if ((rc = batch_upload(b, ones.data()))) break;
+        const int reps = 5;
+        for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_substep(b, 0, b->stream);
+        if (rc) break;
+        if (hipEventRecord(t0, b->stream) != hipSuccess) { rc = hip_fail(hipGetLastError(), "event"); break; }
+        for (int r = 0; r < reps && rc == CLBM_OK; ++r) rc = batch_launch_substep(b, 0, b->stream);
+        if (rc) break;
+        if (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "event");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc) return rc;
+    if ((rc = clbm_batch_set_variant(b, best))) return rc;
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << sig << " " << best << "\n";
+    }
+    return CLBM_OK;
+}
+
+int clbm_batch_destroy(clbm_batch *b)
+{
+    if (!b) return CLBM_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_lats) (void)hipFree(b->d_lats);
+    if (b->h_lats) (void)hipHostFree(b->h_lats);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return CLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// clbm_device.h -- device-side pieces of the D2Q9 cascaded LBM step for gfx950.
+//
+// The per-node collision of Fei & Luo (Eq. 12 with Eqs. 8, 14, 15, then the
+// back-transform of Eq. 9) is evaluated here in closed form: the products
+// with M, N(u), N^-1(u) and M^-1 are expanded by hand into sums over the
+// populations, and everything is carried as deviations from the rest state
+// (f_i - w_i rho0, rho - rho0, moments minus their equilibrium values) so
+// that FP32 keeps its digits for the small departures that matter.
+//
+// Notation: g_i = f_i - w_i rho0 (stored), dr = rho - rho0, j = sum f e,
+// u = (j + F/2)/rho (Eq. 15).  Raw moments of g:
+//   kxx = sum g ex^2, kyy = sum g ey^2, kxy = sum g ex ey,
+//   kxxy = sum g ex^2 ey, kxyy = sum g ex ey^2, kxxyy = sum g ex^2 ey^2.
+// The rest state contributes rho0/3 to k20 and k02 and rho0/9 to k22 and
+// nothing else.  Central moments k~mn (Eq. 2) follow from the binomial
+// shift of the raw ones, with j = rho u - F/2 substituted, which gives the
+// equilibrium-deviation forms used below:
+//   k~20 - rho/3 = kxx - dr/3 - rho ux^2 + ux Fx
+//   k~11         = kxy - rho ux uy + (ux Fy + uy Fx)/2
+//   k~21         = kxxy - 2 ux kxy - uy (kxx + rho0/3) + 2 rho ux^2 uy
+//                  - ux^2 Fy/2 - ux uy Fx
+//   k~22 - rho/9 = kxxyy - dr/9 - 2 ux kxyy - 2 uy kxxy + ux^2 kyy + uy^2 kxx
+//                  + (ux^2 + uy^2) rho0/3 + 4 ux uy kxy - 3 rho ux^2 uy^2
+//                  + ux uy (uy Fx + ux Fy)
+// and symmetric ones with x and y exchanged.  After relaxation the raw
+// moments are rebuilt with the inverse binomial shift (Eq. 9's N^-1) and the
+// populations with M^-1 (Appendix), again as deviations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clbm {
+
+// Eq. (1) order.
+__host__ __device__ constexpr int ex_of(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0; }
+__host__ __device__ constexpr int ey_of(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0; }
+__host__ __device__ constexpr int opp_of(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(3) == 1 && opp_of(4) == 2, "opp");
+static_assert(opp_of(5) == 7 && opp_of(6) == 8 && opp_of(7) == 5 && opp_of(8) == 6, "opp");
+
+// Rest weights w_i = f_i^eq(rho = 1, u = 0).
+template <typename R>
+__device__ __forceinline__ R weight(int i)
+{
+    return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+
+// ---- storage conversions ---------------------------------------------------
+
+enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+template <int ST> struct Storage;
+
+template <> struct Storage<ST_F64> {
+    using T = double;  // stored element
+    using R = double;  // arithmetic
+    static __device__ __forceinline__ R to_r(T v) { return v; }
+    static __device__ __forceinline__ T from_r(R v) { return v; }
+};
+
+template <> struct Storage<ST_F32> {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R to_r(T v) { return v; }
+    static __device__ __forceinline__ T from_r(R v) { return v; }
+};
+
+template <> struct Storage<ST_F16> {
+    using T = _Float16;
+    using R = float;
+    static __device__ __forceinline__ R to_r(T v) { return (float)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }  // RNE
+};
+
+// bfloat16 kept as its raw 16 bits; conversion rounds the FP32 bit pattern
+// to nearest even (NaN stays NaN).
+template <> struct Storage<ST_BF16> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R to_r(T v) { return __uint_as_float(uint32_t(v) << 16); }
+    static __device__ __forceinline__ T from_r(R v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+};
+
+// ---- relaxation parameters in the arithmetic type --------------------------
+
+enum SchemeKind { SCH_CONSISTENT = 0, SCH_GUO_LBL = 1 };
+
+template <typename R>
+struct Rates {
+    R om1;   // 1 - s1
+    R omb;   // 1 - sb
+    R om2;   // 1 - s2
+    R om3;   // 1 - s3
+    R om4;   // 1 - s4
+    R h3;    // 1 - s3/2 (force weight on the third-order slots, Eq. 12)
+    R h2;    // 1 - s2/2 (force weight of Eq. 21)
+    R rho0;
+};
+
+// ---- the node update -------------------------------------------------------
+
+// Back-transform (Eq. 9): from the post-collision central moments, given as
+// deviations, to post-collision deviations g*.
+//   c10, c01 : k~10*, k~01*
+//   p, q     : k~20* - rho/3 and k~02* - rho/3
+//   a5..a8   : k~11*, k~21*, k~12*, k~22* - rho/9
+template <typename R>
+__host__ __device__ __forceinline__ void from_central(R dr, R rho, R ux, R uy, R c10, R c01, R p, R q, R a5,
+                                             R a6, R a7, R a8, R g[9])
+{
+    const R third = R(1) / R(3);
+    const R ninth = R(1) / R(9);
+    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    const R c20 = rho * third + p;  // full k~20*
+    const R c02 = rho * third + q;  // full k~02*
+    // Raw moments (inverse binomial shift) minus the rest-state raw moments.
+    const R r10 = c10 + rho * ux;
+    const R r01 = c01 + rho * uy;
+    const R r20 = dr * third + p + R(2) * ux * c10 + rho * uxx;
+    const R r02 = dr * third + q + R(2) * uy * c01 + rho * uyy;
+    const R r11 = a5 + ux * c01 + uy * c10 + rho * uxy;
+    const R r21 = a6 + R(2) * ux * a5 + uy * c20 + uxx * c01 + R(2) * uxy * c10 + rho * uxx * uy;
+    const R r12 = a7 + R(2) * uy * a5 + ux * c02 + uyy * c10 + R(2) * uxy * c01 + rho * ux * uyy;
+    const R r22 = dr * ninth + a8 + R(2) * ux * a7 + R(2) * uy * a6 + uxx * c02 + uyy * c20 +
+                  R(4) * uxy * a5 + R(2) * ux * uyy * c10 + R(2) * uxx * uy * c01 + rho * uxx * uyy;
+    // M^-1 (Appendix), row by row.
+    const R h = R(0.5), qr = R(0.25);
+    g[0] = dr - (r20 + r02) + r22;
+    g[1] = h * (r10 + r20 - r12 - r22);
+    g[2] = h * (r01 + r02 - r21 - r22);
+    g[3] = h * (-r10 + r20 + r12 - r22);
+    g[4] = h * (-r01 + r02 + r21 - r22);
+    g[5] = qr * (r11 + r21 + r12 + r22);
+    g[6] = qr * (-r11 + r21 - r12 + r22);
+    g[7] = qr * (r11 - r21 - r12 + r22);
+    g[8] = qr * (-r11 - r21 + r12 + r22);
+}
+
+// One collision in place: g holds pre-collision deviations on entry and
+// post-collision deviations on exit.  F is the force density at the node.
+template <typename R, int SCH>
+__host__ __device__ __forceinline__ void collide(R g[9], R Fx, R Fy, const Rates<R> &rt)
+{
+    const R third = R(1) / R(3);
+    const R ninth = R(1) / R(9);
+    const R h = R(0.5);
+
+    // Eq. (11) on deviations, Eq. (15).
+    const R sx = g[1] + g[3];
+    const R sy = g[2] + g[4];
+    const R sd = (g[5] + g[6]) + (g[7] + g[8]);
+    const R dr = g[0] + sx + sy + sd;
+    const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const R rho = rt.rho0 + dr;
+    const R inv = R(1) / rho;
+    const R ux = (jx + h * Fx) * inv;
+    const R uy = (jy + h * Fy) * inv;
+
+    // Raw moments of g above first order.
+    const R kxx = sx + sd;
+    const R kyy = sy + sd;
+    const R kxy = (g[5] + g[7]) - (g[6] + g[8]);
+    const R kxxy = (g[5] + g[6]) - (g[7] + g[8]);
+    const R kxyy = (g[5] + g[8]) - (g[6] + g[7]);
+    const R kxxyy = sd;
+
+    // Central moments as deviations from T~eq (Eq. 8).
+    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    const R r3 = rt.rho0 * third;
+    const R cxx = kxx - dr * third - rho * uxx + ux * Fx;
+    const R cyy = kyy - dr * third - rho * uyy + uy * Fy;
+    const R cxy = kxy - rho * uxy + h * (ux * Fy + uy * Fx);
+    const R cxxy = kxxy - R(2) * ux * kxy - uy * (kxx + r3) + R(2) * rho * uxx * uy - h * uxx * Fy -
+                   uxy * Fx;
+    const R cxyy = kxyy - R(2) * uy * kxy - ux * (kyy + r3) + R(2) * rho * ux * uyy - h * uyy * Fx -
+                   uxy * Fy;
+    const R cxxyy = kxxyy - dr * ninth - R(2) * ux * kxyy - R(2) * uy * kxxy + uxx * kyy + uyy * kxx +
+                    (uxx + uyy) * r3 + R(4) * uxy * kxy - R(3) * rho * uxx * uyy +
+                    uxy * (uy * Fx + ux * Fy);
+
+    // Relaxation, Eq. (12) (or Eq. 21), slot by slot.
+    const R a3 = rt.omb * (cxx + cyy);
+    const R a4 = rt.om2 * (cxx - cyy);
+    const R a5 = rt.om2 * cxy;
+    R a6 = rt.om3 * cxxy;
+    R a7 = rt.om3 * cxyy;
+    R a8 = rt.om4 * cxxyy;
+    R c10, c01;
+    if (SCH == SCH_CONSISTENT) {
+        // Eq. (14): C = [0, Fx, Fy, 0, 0, 0, Fy/3, Fx/3, 0].  The first-order
+        // slots come out at +F/2 whatever s1 is.
+        c10 = h * Fx;
+        c01 = h * Fy;
+        a6 += rt.h3 * (third * Fy);
+        a7 += rt.h3 * (third * Fx);
+    } else {
+        // Eq. (21): central moments of Guo's term, weighted by 1 - s2/2.
+        c10 = -h * rt.om1 * Fx + rt.h2 * Fx;
+        c01 = -h * rt.om1 * Fy + rt.h2 * Fy;
+        a6 += rt.h2 * (third * Fy - R(2) * uxy * Fx - uxx * Fy);
+        a7 += rt.h2 * (third * Fx - uyy * Fx - R(2) * uxy * Fy);
+        a8 += rt.h2 * (R(4) * uxy * (uy * Fx + ux * Fy));
+    }
+    const R p = h * (a3 + a4);
+    const R q = h * (a3 - a4);
+    from_central<R>(dr, rho, ux, uy, c10, c01, p, q, a5, a6, a7, a8, g);
+}
+
+// Pre-collision deviations of the start state (central moments
+// [rho, -Fx/2, -Fy/2, 2 rho/3, 0, 0, 0, 0, rho/9] about u).
+template <typename R>
+__host__ __device__ __forceinline__ void start_state(R rho0, R rho, R ux, R uy, R Fx, R Fy, R g[9])
+{
+    const R h = R(0.5);
+    from_central<R>(rho - rho0, rho, ux, uy, -h * Fx, -h * Fy, R(0), R(0), R(0), R(0), R(0), R(0), g);
+}
+
+}  // namespace clbm

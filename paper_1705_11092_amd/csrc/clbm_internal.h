@@ -1,0 +1,87 @@
+// clbm_internal.h -- types shared by the kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clbm {
+
+// Where the force density of a lattice comes from.
+enum ForceMode {
+    FM_CONST = 0,  // (Fx, Fy) of the descriptor at every node (zero = no force)
+    FM_ROW = 1,    // Fx from a per-row table, Fy = 0 (Kolmogorov forcing)
+    FM_FIELD = 2   // fx, fy planes [ny][nx] in the arithmetic type
+};
+
+// Threads per block of every step kernel.
+constexpr int kBlock = 256;
+
+// Row padding: each row starts on a multiple of kRowAlign elements so that
+// the vector stores of every storage type are naturally aligned.
+constexpr int kRowAlign = 8;
+
+// Everything a kernel needs to step one lattice.  Passed by value to the
+// single-lattice kernel and stored in a device array for batches.
+struct LatDesc {
+    void *buf[2];        // ping-pong population buffers
+    const void *force;   // FM_ROW: table[ny]; FM_FIELD: fx plane then fy plane
+    int64_t plane;       // elements between population planes
+    int32_t nx, ny;      // lattice size
+    int32_t pitch;       // elements between rows
+    int32_t bc_y;        // 0 periodic, 1 half-way bounce-back
+    int32_t storage;     // StorageKind
+    int32_t force_mode;  // ForceMode
+    int32_t scheme;      // SchemeKind
+    int32_t parity;      // batch: buffer holding the state at sequence start
+    int32_t steps;       // batch: steps of this lattice in the sequence
+    int32_t tpr;         // threads per row inside one tile
+    int32_t rows;        // rows per tile
+    int32_t segs;        // tiles across one row
+    int32_t vec;         // nodes per thread along x
+    int32_t pad_;
+    double Fx, Fy;       // FM_CONST force density
+    double rho0;
+    double om1, omb, om2, om3, om4, h3, h2;  // 1 - s and force weights
+};
+
+// A tile of a batch: tile index t of lattice lat (row group = t / segs,
+// segment = t % segs).
+struct Tile {
+    int32_t lat;
+    int32_t t;
+};
+
+// Tile geometry of one lattice for a block of kBlock threads and vec nodes
+// per thread.
+inline void tile_geometry(int nx, int ny, int vec, int32_t *tpr, int32_t *rows, int32_t *segs,
+                          int64_t *ntiles)
+{
+    const int slots = (nx + vec - 1) / vec;
+    const int t = slots < kBlock ? slots : kBlock;
+    *tpr = t;
+    *rows = kBlock / t;
+    *segs = (slots + t - 1) / t;
+    *ntiles = (int64_t)(*segs) * ((ny + *rows - 1) / *rows);
+}
+
+// Launchers (clbm_kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s);
+hipError_t launch_batch(const LatDesc *lats, const Tile *tiles, int64_t ntiles, int storage, int vec,
+                        int grid, int substep, hipStream_t s);
+hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s);
+hipError_t launch_init(const LatDesc &d, int dst, const double *rho, const double *ux,
+                       const double *uy, hipStream_t s);
+hipError_t launch_set_populations(const LatDesc &d, int dst, const double *f, hipStream_t s);
+hipError_t launch_get_populations(const LatDesc &d, int src, double *f, hipStream_t s);
+// Moments and FP64 partial sums; returns the number of partial blocks.
+hipError_t launch_moments(const LatDesc &d, int src, double *rho, double *ux, double *uy,
+                          const double *ux_ref, const double *uy_ref, double *partials,
+                          int *nblocks, hipStream_t s);
+hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s);
+hipError_t launch_force_table(const LatDesc &d, void *table, double A, double k, hipStream_t s);
+hipError_t launch_force_field(const LatDesc &d, void *field, const double *fx, const double *fy,
+                              hipStream_t s);
+// Partial blocks the moments kernel uses for a lattice of n nodes.
+int moments_blocks(int64_t n);
+
+}  // namespace clbm
