@@ -9,7 +9,13 @@ lattice (Eqs. 9-15).  Inputs are resident in HBM before timing starts.
 Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
 algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
 oracle's throughput on the host cores for a bounded sample of the same
-workload.
+workload.  Beside it, in the same line: the same lattice with 16-bit
+storage, the batch of 256 uneven Kolmogorov lattices advanced by one
+persistent launch per step, and a served Poisson stream of solves with its
+p50/p99 latency.
+
+`--calibrate-copy` instead runs a plain device copy of known size (the
+reference for scaling the HBM byte counters of rocprofv3).
 """
 from __future__ import annotations
 
@@ -79,6 +85,71 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
     return ms, wall, tot
 
 
+def run_batch(steps: int, warmup: int, count: int = 256):
+    """The batch of uneven Kolmogorov lattices (sides log-uniform in
+    [32, 512], seed 0), FP32 storage, one persistent launch per step."""
+    import torch
+    from paper_1705_11092_amd import clbm, inputs
+
+    wls = inputs.kolmogorov_batch(count=count, seed=0, steps=steps)
+    lats = [clbm.lattice_from_workload(wl, storage="f32") for wl in wls]
+    b = clbm.Batch(lats)
+    variant = b.autotune(None)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(b.stream)
+    b.step(steps)
+    t1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    nodes = sum(wl.nx * wl.ny for wl in wls)
+    b.close()
+    for lat in lats:
+        lat.close()
+    torch.cuda.empty_cache()
+    mlups = nodes * steps / (ms / 1e3) / 1e6
+    return {"workload": f"{count} Kolmogorov lattices, sides log-uniform 32..512 (seed 0), f32",
+            "nodes": nodes, "steps": steps, "ms_per_step": round(ms / steps, 5),
+            "mlups": round(mlups, 1), "hbm_frac": round(mlups * 1e6 * 72 / 8e12, 4),
+            "variant": variant}
+
+
+def run_served(count: int):
+    """A Poisson stream of solves at ~80 % of the measured saturation rate."""
+    import torch
+    from paper_1705_11092_amd import inputs
+    from paper_1705_11092_amd.serve import GpuBackend, Server
+
+    # Saturation: the same kind of stream with every request waiting at t = 0.
+    sat = inputs.served_stream(count=count, seed=2, rate=1e9)
+    rep = Server(GpuBackend()).run(sat)
+    mu = rep.summary()["done"] / rep.makespan
+    torch.cuda.empty_cache()
+    reqs = inputs.served_stream(count=count, seed=1, rate=0.8 * mu)
+    rep = Server(GpuBackend()).run(reqs)
+    s = rep.summary()
+    torch.cuda.empty_cache()
+    return {"workload": f"{count} solves, sides log-uniform 64..2048, steps log-uniform 1e3..1e5, "
+                        "forcing const/kolmogorov/none, f32 or f16 storage, Poisson arrivals",
+            "saturation_rps": round(mu, 3), "arrival_rps": round(0.8 * mu, 3),
+            "p50_latency_s": round(s["p50_latency_s"], 4), "p99_latency_s": round(s["p99_latency_s"], 4),
+            "mlups": round(s["mlups"], 1), "done": s["done"], "rejected": s["rejected"],
+            "makespan_s": round(s["makespan_s"], 3), "max_active": s["max_active"]}
+
+
+def calibrate_copy(nbytes: int, reps: int):
+    """A plain device-to-device copy of nbytes, reps times."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle on the host cores: the same 4096^2 workload, as many steps
     as fit in about budget_s seconds after one timed probe step."""
@@ -108,7 +179,15 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the main lattice (16-bit, batch and served legs skipped)")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy, 5)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
@@ -146,6 +225,17 @@ def main():
         "wall_s": round(wall, 4),
         "mass_total": tot[0],
     }
+    if not args.no_extra:
+        extra = {}
+        for st in ("f16", "bf16"):
+            ms16, _, _ = run_gpu(args.n, st, args.steps, args.warmup)
+            m = nodes / (ms16 / args.steps / 1e3) / 1e6
+            extra[st] = {"mlups": round(m, 1), "ms_per_step": round(ms16 / args.steps, 5),
+                         "hbm_frac": round(m * 1e6 * BYTES_PER_LUP[st] / 8e12, 4)}
+        extra["batch"] = run_batch(1000, 20)
+        if args.serve_requests > 0:
+            extra["served"] = run_served(args.serve_requests)
+        line["also"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(line), flush=True)

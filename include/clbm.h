@@ -104,13 +104,16 @@ typedef struct {
 size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage);
 
 /* Validate cfg and create a handle.  Allocates the FP64 reduction scratch
- * (a few KB of device memory) and pinned host memory for the totals.
+ * (at most 24 KB of device memory, stream-ordered on cfg->stream).
  * Errors: CLBM_EINVAL (any field out of range, null buffers, pop_a ==
- * pop_b), CLBM_EHIP. */
+ * pop_b, buffers that are not device memory or smaller than
+ * clbm_buffer_bytes), CLBM_EHIP. */
 int clbm_create(const clbm_config *cfg, clbm_handle **out);
 
-/* Wait for the handle's stream, release the handle and what it owns.
- * Accepts NULL. */
+/* Release the handle without waiting for the device: the device memory it
+ * owns is freed in stream order and its graphs once their last launch has
+ * completed.  The caller's buffers may be reused by work queued later on the
+ * same stream.  Accepts NULL. */
 int clbm_destroy(clbm_handle *h);
 
 /* Set the body force F(x) of Eqs. (12)-(15).  CONST and KOLMOGOROV read
@@ -118,6 +121,8 @@ int clbm_destroy(clbm_handle *h);
  * [ny][nx]) into a library-owned device buffer in the arithmetic type, so
  * the caller may free them once the stream has passed this call.  A new
  * force applies from the next step; clbm_init uses the force set before it.
+ * Does not wait for the device (buffers are allocated and freed in stream
+ * order).
  * Errors: CLBM_EINVAL (unknown kind, missing params or arrays, non-finite
  * values), CLBM_EHIP. */
 int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const double *fx,
@@ -189,8 +194,10 @@ typedef struct clbm_batch clbm_batch;
 
 /* Build a batch over count >= 1 existing handles (not owned; they must
  * outlive the batch, and while the batch exists they must be stepped only
- * through it).  All work goes to stream.  Allocates the device tile list
- * and lattice table.  Errors: CLBM_EINVAL (duplicates, NULLs), CLBM_EHIP. */
+ * through it).  All work goes to stream, which must be the stream of every
+ * lattice.  Allocates the device lattice table (stream-ordered).  The force
+ * and state of each lattice are read at every step call.
+ * Errors: CLBM_EINVAL (duplicates, NULLs), CLBM_EHIP. */
 int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream,
                       clbm_batch **out);
 
@@ -212,7 +219,8 @@ int32_t clbm_batch_variant_count(void);
 int clbm_batch_set_variant(clbm_batch *b, int32_t variant);
 int32_t clbm_batch_get_variant(const clbm_batch *b);
 
-/* Release the batch (not its lattices).  Accepts NULL. */
+/* Release the batch (not its lattices) without waiting for the device.
+ * Accepts NULL. */
 int clbm_batch_destroy(clbm_batch *b);
 
 #ifdef __cplusplus

@@ -191,7 +191,8 @@ class Lattice:
         with torch.cuda.stream(self.stream):
             tr, tu, tv = (_field(a, shape, self.device) for a in (rho, ux, uy))
             _check(lib.clbm_init(self._h, _ptr(tr), _ptr(tu), _ptr(tv)))
-            self.stream.synchronize()
+        # The input fields are freed into torch's allocator on this stream, so
+        # later work on the stream cannot reuse them before the kernel reads.
         return self
 
     def step(self, n: int = 1):
@@ -240,7 +241,6 @@ class Lattice:
         with torch.cuda.stream(self.stream):
             t = _field(f, (9, self.ny, self.nx), self.device)
             _check(lib.clbm_set_populations(self._h, _ptr(t)))
-            self.stream.synchronize()
         return self
 
 

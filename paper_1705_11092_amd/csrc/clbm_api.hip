@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -16,7 +17,6 @@
 #include "clbm_internal.h"
 
 using clbm::LatDesc;
-using clbm::Tile;
 
 // Extra elements between population planes (skews the nine streams across
 // HBM channels; 0 keeps planes back to back).
@@ -102,6 +102,55 @@ int check_device_range(const void *p, size_t bytes, const char *name)
     return CLBM_OK;
 }
 
+// Graphs that may still be queued are not destroyed at once: each is kept
+// with an event recorded after its last launch and destroyed once that event
+// has completed.  No call of this library waits for the device to drain.
+std::mutex g_retire_mu;
+std::vector<std::pair<hipGraphExec_t, hipEvent_t>> g_retired;
+
+void reap_retired()
+{
+    std::lock_guard<std::mutex> lk(g_retire_mu);
+    for (size_t k = 0; k < g_retired.size();) {
+        if (hipEventQuery(g_retired[k].second) == hipSuccess) {
+            (void)hipGraphExecDestroy(g_retired[k].first);
+            (void)hipEventDestroy(g_retired[k].second);
+            g_retired[k] = g_retired.back();
+            g_retired.pop_back();
+        } else {
+            ++k;
+        }
+    }
+    (void)hipGetLastError();
+}
+
+void retire_graph(hipGraphExec_t g, hipStream_t s)
+{
+    if (!g) return;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess) {
+        // Without an event, wait for the stream once rather than risk
+        // destroying a queued graph.
+        (void)hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(g);
+        if (ev) (void)hipEventDestroy(ev);
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_retire_mu);
+    g_retired.emplace_back(g, ev);
+}
+
+// Pinned host words for the FP64 totals, one set per host thread for the
+// life of the process (the calls that use them wait for their stream).
+double *pinned_words()
+{
+    static thread_local double *p = nullptr;
+    if (!p && hipHostMalloc(&p, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
+}
+
 }  // namespace
 
 // ---- handle ----------------------------------------------------------------
@@ -114,10 +163,9 @@ struct clbm_handle {
     int parity = 0;             // buffer holding the current state
     int64_t steps = 0;
     bool ready = false;
-    void *force_buf = nullptr;
-    double *partials = nullptr;  // per-block FP64 partial sums
+    void *force_buf = nullptr;   // stream-ordered allocation
+    double *partials = nullptr;  // per-block FP64 partial sums (stream-ordered)
     double *d_out = nullptr;     // reduced totals on the device
-    double *h_out = nullptr;     // pinned copy of the totals
     int vec = 4;
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -128,7 +176,7 @@ namespace {
 void drop_graphs(clbm_handle *h)
 {
     for (int p = 0; p < 2; ++p) {
-        if (h->graph[p]) (void)hipGraphExecDestroy(h->graph[p]);
+        retire_graph(h->graph[p], h->stream);
         h->graph[p] = nullptr;
     }
 }
@@ -136,6 +184,7 @@ void drop_graphs(clbm_handle *h)
 int build_graph(clbm_handle *h, int parity)
 {
     hipGraph_t g = nullptr;
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
@@ -221,11 +270,11 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.h2 = 1.0 - 0.5 * cfg->s2;
     h->vec = default_vec(cfg->storage);
 
+    reap_retired();
     const int nb = clbm::moments_blocks((int64_t)cfg->nx * cfg->ny);
-    hipError_t e = hipMalloc(&h->partials, sizeof(double) * (3 * (size_t)nb + 3));
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&h->partials),
+                                  sizeof(double) * (3 * (size_t)nb + 3), h->stream);
     if (e == hipSuccess) h->d_out = h->partials + 3 * (size_t)nb;
-    if (e == hipSuccess) e = hipHostMalloc(&h->h_out, 3 * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         clbm_destroy(h);
         return hip_fail(e, "clbm_create allocations");
@@ -237,13 +286,13 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
 int clbm_destroy(clbm_handle *h)
 {
     if (!h) return CLBM_OK;
-    if (h->stream || h->ready) (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
-    if (h->force_buf) (void)hipFree(h->force_buf);
-    if (h->partials) (void)hipFree(h->partials);
-    if (h->h_out) (void)hipHostFree(h->h_out);
+    if (h->force_buf) (void)hipFreeAsync(h->force_buf, h->stream);
+    if (h->partials) (void)hipFreeAsync(h->partials, h->stream);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    (void)hipGetLastError();
     delete h;
+    reap_retired();
     return CLBM_OK;
 }
 
@@ -283,11 +332,10 @@ int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const dou
             rc = check_device_range(fy, sizeof(double) * n, "fy");
             if (rc) return rc;
         }
-        // The old table may still be read by queued steps.
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (h->force_buf) HIPCHK(hipFree(h->force_buf));
+        // Queued steps may still read the old table: free it in stream order.
+        if (h->force_buf) HIPCHK(hipFreeAsync(h->force_buf, h->stream));
         h->force_buf = nullptr;
-        HIPCHK(hipMalloc(&h->force_buf, bytes));
+        HIPCHK(hipMallocAsync(&h->force_buf, bytes, h->stream));
         if (kind == CLBM_FORCE_KOLMOGOROV) {
             d.force_mode = clbm::FM_ROW;
             HIPCHK(clbm::launch_force_table(d, h->force_buf, params[0], params[1], h->stream));
@@ -359,12 +407,14 @@ int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *to
     HIPCHK(clbm::launch_moments(h->d, h->parity, rho, ux, uy, nullptr, nullptr, h->partials, &nb,
                                 h->stream));
     if (!totals) return CLBM_OK;
+    double *w = pinned_words();
+    if (!w) return fail(CLBM_EHIP, "pinned host memory for the totals");
     HIPCHK(clbm::launch_reduce(h->partials, nb, 3, h->d_out, h->stream));
-    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(w, h->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    totals[0] = (double)h->d.nx * h->d.ny * h->d.rho0 + h->h_out[0];
-    totals[1] = h->h_out[1];
-    totals[2] = h->h_out[2];
+    totals[0] = (double)h->d.nx * h->d.ny * h->d.rho0 + w[0];
+    totals[1] = w[1];
+    totals[2] = w[2];
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(totals[c])) return fail(CLBM_ENONFINITE, "mass or momentum is not finite");
     return CLBM_OK;
@@ -382,11 +432,13 @@ int clbm_error_norms(clbm_handle *h, const double *ux_ref, const double *uy_ref,
     int nb = 0;
     HIPCHK(clbm::launch_moments(h->d, h->parity, nullptr, nullptr, nullptr, ux_ref, uy_ref,
                                 h->partials, &nb, h->stream));
+    double *w = pinned_words();
+    if (!w) return fail(CLBM_EHIP, "pinned host memory for the norms");
     HIPCHK(clbm::launch_reduce(h->partials, nb, 2, h->d_out, h->stream));
-    HIPCHK(hipMemcpyAsync(h->h_out, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(w, h->d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    out[0] = h->h_out[0];
-    out[1] = h->h_out[1];
+    out[0] = w[0];
+    out[1] = w[1];
     return CLBM_OK;
 }
 
@@ -459,92 +511,86 @@ int vec_for(int storage, int vec_bytes)
 }  // namespace
 
 struct clbm_batch {
-    std::vector<clbm_handle *> lats;
+    std::vector<clbm_handle *> lats;  // caller's order
+    std::vector<int> order;           // table position -> caller index (grouped by storage)
     hipStream_t stream = nullptr;
-    hipStream_t cap = nullptr;
-    LatDesc *d_lats = nullptr;  // device lattice table
-    LatDesc *h_lats = nullptr;  // pinned staging of the table
-    hipEvent_t staged = nullptr;  // last upload from h_lats
-    bool staged_pending = false;
-    Tile *d_tiles = nullptr;
+    hipStream_t cap = nullptr;        // capture-only stream, created on first graph
+    LatDesc *d_lats = nullptr;        // device lattice table (stream-ordered)
     struct Group {
-        int storage, vec;
-        int64_t first, count;
+        int storage, vec, l_lo, l_hi;
+        int64_t ntiles;
     };
     std::vector<Group> groups;
+    std::vector<LatDesc> tab;         // host copy of the table's geometry
     int variant = 0;
     int cus = 256;
-    int chunk = 32;  // launches per captured graph
+    int chunk = 32;                   // launches per captured graph
     hipGraphExec_t graph = nullptr;
 };
 
 namespace {
 
-void batch_drop_graph(clbm_batch *b)
+// Geometry of the current variant: per lattice nodes per thread, tile
+// shape and first tile; per storage group its lattice range and tile count.
+void batch_geometry(clbm_batch *b)
 {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->groups.clear();
+    b->tab.assign(b->order.size(), LatDesc());
+    size_t pos = 0;
+    while (pos < b->order.size()) {
+        const int st = b->lats[b->order[pos]]->d.storage;
+        const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
+        const int lo = (int)pos;
+        int64_t tiles = 0;
+        while (pos < b->order.size() && b->lats[b->order[pos]]->d.storage == st) {
+            LatDesc d = b->lats[b->order[pos]]->d;
+            clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.rows, &d.segs, &d.ntiles);
+            d.vec = vec;
+            d.tile0 = tiles;
+            tiles += d.ntiles;
+            b->tab[pos] = d;
+            ++pos;
+        }
+        b->groups.push_back({st, vec, lo, (int)pos, tiles});
+    }
+    retire_graph(b->graph, b->stream);
     b->graph = nullptr;
 }
 
-// Tile lists of the current variant, grouped by storage type.
-int batch_build_tiles(clbm_batch *b)
-{
-    std::vector<Tile> tiles;
-    b->groups.clear();
-    for (int st = 0; st < 4; ++st) {
-        const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
-        const int64_t first = (int64_t)tiles.size();
-        for (size_t j = 0; j < b->lats.size(); ++j) {
-            const LatDesc &d = b->lats[j]->d;
-            if (d.storage != st) continue;
-            int32_t tpr, rows, segs;
-            int64_t nt;
-            clbm::tile_geometry(d.nx, d.ny, vec, &tpr, &rows, &segs, &nt);
-            for (int64_t t = 0; t < nt; ++t) tiles.push_back(Tile{(int32_t)j, (int32_t)t});
-        }
-        if ((int64_t)tiles.size() > first)
-            b->groups.push_back({st, vec, first, (int64_t)tiles.size() - first});
-    }
-    if (b->d_tiles) {
-        HIPCHK(hipStreamSynchronize(b->stream));
-        HIPCHK(hipFree(b->d_tiles));
-        b->d_tiles = nullptr;
-    }
-    HIPCHK(hipMalloc(&b->d_tiles, sizeof(Tile) * tiles.size()));
-    HIPCHK(hipMemcpy(b->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
-    batch_drop_graph(b);
-    return CLBM_OK;
-}
-
-// Copy the lattices' descriptors, with their current parity and the steps
-// each takes in this call, to the device table.
+// Refresh the table from the lattices (force, parity) with the steps each
+// takes in this call, and send it to the device through kernel arguments.
 int batch_upload(clbm_batch *b, const int64_t *nsteps)
 {
-    if (b->staged_pending) HIPCHK(hipEventSynchronize(b->staged));
-    for (size_t j = 0; j < b->lats.size(); ++j) {
-        const clbm_handle *h = b->lats[j];
-        LatDesc d = h->d;
-        const int vec = vec_for(d.storage, kVariants[b->variant].vec_bytes);
-        int64_t nt;
-        clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.rows, &d.segs, &nt);
-        d.vec = vec;
-        d.parity = h->parity;
-        d.steps = (int32_t)nsteps[j];
-        b->h_lats[j] = d;
+    clbm::UploadPayload p;
+    const int count = (int)b->order.size();
+    for (int first = 0; first < count; first += clbm::kUploadMax) {
+        const int n = std::min(clbm::kUploadMax, count - first);
+        for (int k = 0; k < n; ++k) {
+            const int pos = first + k;
+            const clbm_handle *h = b->lats[b->order[pos]];
+            LatDesc d = h->d;
+            const LatDesc &g = b->tab[pos];
+            d.tpr = g.tpr;
+            d.rows = g.rows;
+            d.segs = g.segs;
+            d.vec = g.vec;
+            d.tile0 = g.tile0;
+            d.ntiles = g.ntiles;
+            d.parity = h->parity;
+            d.steps = (int32_t)nsteps[b->order[pos]];
+            p.d[k] = d;
+        }
+        HIPCHK(clbm::launch_upload(b->d_lats, first, n, p, b->stream));
     }
-    HIPCHK(hipMemcpyAsync(b->d_lats, b->h_lats, sizeof(LatDesc) * b->lats.size(),
-                          hipMemcpyHostToDevice, b->stream));
-    HIPCHK(hipEventRecord(b->staged, b->stream));
-    b->staged_pending = true;
     return CLBM_OK;
 }
 
 int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
 {
-    const int grid = b->cus * kVariants[b->variant].blocks_per_cu;
+    const int64_t grid = (int64_t)b->cus * kVariants[b->variant].blocks_per_cu;
     for (const auto &g : b->groups) {
-        const int gg = (int)std::min<int64_t>(grid, g.count);
-        HIPCHK(clbm::launch_batch(b->d_lats, b->d_tiles + g.first, g.count, g.storage, g.vec, gg,
+        const int gg = (int)std::min<int64_t>(grid, g.ntiles);
+        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.vec, gg,
                                   substep, s));
     }
     return CLBM_OK;
@@ -553,11 +599,12 @@ int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
 int batch_build_graph(clbm_batch *b)
 {
     hipGraph_t g = nullptr;
+    if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     int rc = CLBM_OK;
     for (int k = 0; k < b->chunk && rc == CLBM_OK; ++k) rc = batch_launch_substep(b, k, b->cap);
     hipError_t le = rc == CLBM_OK
-                        ? clbm::launch_batch_advance(b->d_lats, (int)b->lats.size(), b->chunk, b->cap)
+                        ? clbm::launch_batch_advance(b->d_lats, (int)b->order.size(), b->chunk, b->cap)
                         : hipSuccess;
     hipError_t ce = hipStreamEndCapture(b->cap, &g);
     if (rc != CLBM_OK || le != hipSuccess) {
@@ -593,7 +640,7 @@ int batch_run(clbm_batch *b, const int64_t *nsteps)
     if (left > 0) {
         for (int k = 0; k < left; ++k)
             if ((rc = batch_launch_substep(b, k, b->stream))) return rc;
-        HIPCHK(clbm::launch_batch_advance(b->d_lats, (int)b->lats.size(), (int)left, b->stream));
+        HIPCHK(clbm::launch_batch_advance(b->d_lats, (int)b->order.size(), (int)left, b->stream));
     }
     for (size_t j = 0; j < b->lats.size(); ++j) {
         b->lats[j]->parity = (int)((b->lats[j]->parity + nsteps[j]) & 1);
@@ -642,26 +689,24 @@ int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream,
         for (int k = 0; k < j; ++k)
             if (v[k] == v[j]) return fail(CLBM_EINVAL, "a lattice appears twice in the batch");
     }
+    reap_retired();
     clbm_batch *b = new clbm_batch();
     b->lats = v;
     b->stream = static_cast<hipStream_t>(stream);
+    for (int st = 0; st < 4; ++st)
+        for (int j = 0; j < count; ++j)
+            if (v[j]->d.storage == st) b->order.push_back(j);
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (b->cus < 1) b->cus = 256;
-    hipError_t e = hipMalloc(&b->d_lats, sizeof(LatDesc) * count);
-    if (e == hipSuccess) e = hipHostMalloc(&b->h_lats, sizeof(LatDesc) * count, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&b->d_lats), sizeof(LatDesc) * count,
+                                  b->stream);
     if (e != hipSuccess) {
-        clbm_batch_destroy(b);
-        return hip_fail(e, "clbm_batch_create allocations");
+        delete b;
+        return hip_fail(e, "clbm_batch_create allocation");
     }
-    int rc = batch_build_tiles(b);
-    if (rc) {
-        clbm_batch_destroy(b);
-        return rc;
-    }
+    batch_geometry(b);
     *out = b;
     return CLBM_OK;
 }
@@ -690,7 +735,8 @@ int clbm_batch_set_variant(clbm_batch *b, int32_t variant)
     if (variant < 0 || variant >= kNumVariants) return fail(CLBM_EINVAL, "variant out of range");
     if (variant == b->variant) return CLBM_OK;
     b->variant = variant;
-    return batch_build_tiles(b);
+    batch_geometry(b);
+    return CLBM_OK;
 }
 
 int32_t clbm_batch_get_variant(const clbm_batch *b) { return b ? b->variant : -1; }
@@ -719,7 +765,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     // lattices, so the state is untouched (the next real step overwrites
     // that buffer).
     std::vector<int64_t> ones(b->lats.size(), 1);
-    hipEvent_t t0, t1;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
     int best = b->variant;
@@ -731,11 +777,14 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
         const int reps = 5;
         for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_substep(b, 0, b->stream);
         if (rc) break;
-        if (hipEventRecord(t0, b->stream) != hipSuccess) { rc = hip_fail(hipGetLastError(), "event"); break; }
-        for (int r = 0; r < reps && rc == CLBM_OK; ++r) rc = batch_launch_substep(b, 0, b->stream);
+        hipError_t e = hipEventRecord(t0, b->stream);
+        for (int r = 0; r < reps && rc == CLBM_OK && e == hipSuccess; ++r)
+            rc = batch_launch_substep(b, 0, b->stream);
         if (rc) break;
-        if (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
-            rc = hip_fail(hipGetLastError(), "event");
+        if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune events");
             break;
         }
         float ms = 0.f;
@@ -760,14 +809,12 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
 int clbm_batch_destroy(clbm_batch *b)
 {
     if (!b) return CLBM_OK;
-    (void)hipStreamSynchronize(b->stream);
-    batch_drop_graph(b);
-    if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->d_lats) (void)hipFree(b->d_lats);
-    if (b->h_lats) (void)hipHostFree(b->h_lats);
-    if (b->staged) (void)hipEventDestroy(b->staged);
+    retire_graph(b->graph, b->stream);
+    if (b->d_lats) (void)hipFreeAsync(b->d_lats, b->stream);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipGetLastError();
     delete b;
+    reap_retired();
     return CLBM_OK;
 }
 

@@ -39,16 +39,17 @@ struct LatDesc {
     int32_t segs;        // tiles across one row
     int32_t vec;         // nodes per thread along x
     int32_t pad_;
+    int64_t tile0;       // batch: first tile of this lattice in its group
+    int64_t ntiles;      // batch: tiles of this lattice
     double Fx, Fy;       // FM_CONST force density
     double rho0;
     double om1, omb, om2, om3, om4, h3, h2;  // 1 - s and force weights
 };
 
-// A tile of a batch: tile index t of lattice lat (row group = t / segs,
-// segment = t % segs).
-struct Tile {
-    int32_t lat;
-    int32_t t;
+// Lattice descriptors carried in one upload kernel's arguments.
+constexpr int kUploadMax = 12;
+struct UploadPayload {
+    LatDesc d[kUploadMax];
 };
 
 // Tile geometry of one lattice for a block of kBlock threads and vec nodes
@@ -66,8 +67,12 @@ inline void tile_geometry(int nx, int ny, int vec, int32_t *tpr, int32_t *rows, 
 
 // Launchers (clbm_kernels.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s);
-hipError_t launch_batch(const LatDesc *lats, const Tile *tiles, int64_t ntiles, int storage, int vec,
-                        int grid, int substep, hipStream_t s);
+// One time step of lattices [l_lo, l_hi) of a batch table (all of one
+// storage type, tiles numbered consecutively through their tile0 fields).
+hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
+                        int vec, int grid, int substep, hipStream_t s);
+// Write n <= kUploadMax descriptors to lats[first..first+n) on the stream.
+hipError_t launch_upload(LatDesc *lats, int first, int n, const UploadPayload &p, hipStream_t s);
 hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s);
 hipError_t launch_init(const LatDesc &d, int dst, const double *rho, const double *ux,
                        const double *uy, hipStream_t s);

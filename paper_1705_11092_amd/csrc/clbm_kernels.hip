@@ -224,22 +224,34 @@ __global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t nti
 
 // One time step of every lattice of a batch whose step count exceeds
 // `substep`.  Persistent: block b takes one contiguous chunk of the tile
-// list (tiles are sorted by lattice and row, so a block walks down rows).
+// range of lattices [l_lo, l_hi) (numbered lattice by lattice, row group by
+// row group), so a block walks down the rows of one lattice and on to the
+// next.
 template <int ST, int VEC>
-__global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats,
-                                                  const Tile *__restrict__ tiles, int64_t ntiles,
-                                                  int substep)
+__global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats, int l_lo,
+                                                  int l_hi, int64_t ntiles, int substep)
 {
     const int64_t G = gridDim.x;
     const int64_t b = xcd_order(blockIdx.x, G);
     const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
+    if (lo >= hi) return;
+    // Lattice holding tile lo: last j with tile0 <= lo.
+    int a = l_lo, z = l_hi - 1;
+    while (a < z) {
+        const int m = (a + z + 1) >> 1;
+        if (lats[m].tile0 <= lo)
+            a = m;
+        else
+            z = m - 1;
+    }
+    int j = a;
     for (int64_t t = lo; t < hi; ++t) {
-        const Tile tl = tiles[t];
-        const LatDesc &d = lats[tl.lat];
-        if (substep >= d.steps || d.storage != ST) continue;
+        while (t >= lats[j].tile0 + lats[j].ntiles) ++j;
+        const LatDesc &d = lats[j];
+        if (substep >= d.steps) continue;
         const int src = (d.parity + substep) & 1;
         int y, x0;
-        if (!decode(d, tl.t, threadIdx.x, y, x0)) continue;
+        if (!decode(d, t - d.tile0, threadIdx.x, y, x0)) continue;
         switch (d.force_mode * 2 + d.scheme) {
         case FM_CONST * 2 + SCH_CONSISTENT:
             step_group<ST, VEC, FM_CONST, SCH_CONSISTENT>(d, src, y, x0);
@@ -261,6 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ la
             break;
         }
     }
+}
+
+// Copy descriptors from the kernel's arguments into the device table, so a
+// host staging buffer never has to outlive the call.
+__global__ void k_upload(LatDesc *lats, int first, int n, UploadPayload p)
+{
+    const int j = threadIdx.x;
+    if (j < n) lats[first + j] = p.d[j];
 }
 
 // After a chunk of `chunk` batch launches: advance each lattice's parity by
@@ -505,10 +525,10 @@ hipError_t step_dispatch(const LatDesc &d, int src, hipStream_t s)
 }
 
 template <int ST, int VEC>
-hipError_t batch_dispatch(const LatDesc *lats, const Tile *tiles, int64_t ntiles, int grid,
+hipError_t batch_dispatch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int grid,
                           int substep, hipStream_t s)
 {
-    k_batch<ST, VEC><<<dim3((unsigned)grid), dim3(kBlock), 0, s>>>(lats, tiles, ntiles, substep);
+    k_batch<ST, VEC><<<dim3((unsigned)grid), dim3(kBlock), 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
     return hipGetLastError();
 }
 
@@ -538,28 +558,35 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s)
     }
 }
 
-hipError_t launch_batch(const LatDesc *lats, const Tile *tiles, int64_t ntiles, int storage, int vec,
-                        int grid, int substep, hipStream_t s)
+hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
+                        int vec, int grid, int substep, hipStream_t s)
 {
+#define CLBM_B(ST, V) batch_dispatch<ST, V>(lats, l_lo, l_hi, ntiles, grid, substep, s)
     switch (storage) {
     case ST_F64:
-        return vec == 1 ? batch_dispatch<ST_F64, 1>(lats, tiles, ntiles, grid, substep, s)
-                        : batch_dispatch<ST_F64, 2>(lats, tiles, ntiles, grid, substep, s);
+        return vec == 1 ? CLBM_B(ST_F64, 1) : CLBM_B(ST_F64, 2);
     case ST_F32:
-        return vec == 1   ? batch_dispatch<ST_F32, 1>(lats, tiles, ntiles, grid, substep, s)
-               : vec == 2 ? batch_dispatch<ST_F32, 2>(lats, tiles, ntiles, grid, substep, s)
-                          : batch_dispatch<ST_F32, 4>(lats, tiles, ntiles, grid, substep, s);
+        return vec == 1 ? CLBM_B(ST_F32, 1) : vec == 2 ? CLBM_B(ST_F32, 2) : CLBM_B(ST_F32, 4);
     case ST_F16:
-        return vec == 2   ? batch_dispatch<ST_F16, 2>(lats, tiles, ntiles, grid, substep, s)
-               : vec == 4 ? batch_dispatch<ST_F16, 4>(lats, tiles, ntiles, grid, substep, s)
-                          : batch_dispatch<ST_F16, 8>(lats, tiles, ntiles, grid, substep, s);
+        return vec == 2 ? CLBM_B(ST_F16, 2) : vec == 4 ? CLBM_B(ST_F16, 4) : CLBM_B(ST_F16, 8);
     case ST_BF16:
-        return vec == 2   ? batch_dispatch<ST_BF16, 2>(lats, tiles, ntiles, grid, substep, s)
-               : vec == 4 ? batch_dispatch<ST_BF16, 4>(lats, tiles, ntiles, grid, substep, s)
-                          : batch_dispatch<ST_BF16, 8>(lats, tiles, ntiles, grid, substep, s);
+        return vec == 2 ? CLBM_B(ST_BF16, 2) : vec == 4 ? CLBM_B(ST_BF16, 4) : CLBM_B(ST_BF16, 8);
     default:
         return hipErrorInvalidValue;
     }
+#undef CLBM_B
+}
+
+hipError_t launch_upload(LatDesc *lats, int first, int n, const UploadPayload &p, hipStream_t s)
+{
+    k_upload<<<1, 64, 0, s>>>(lats, first, n, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s)
+{
+    k_batch_advance<<<(count + 255) / 256, 256, 0, s>>>(lats, count, chunk);
+    return hipGetLastError();
 }
 
 #define CLBM_BY_STORAGE(KERNEL, GRID, ...)                                                   \
@@ -570,12 +597,6 @@ hipError_t launch_batch(const LatDesc *lats, const Tile *tiles, int64_t ntiles, 
     case ST_BF16: KERNEL<ST_BF16><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;             \
     default: return hipErrorInvalidValue;                                                    \
     }
-
-hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s)
-{
-    k_batch_advance<<<(count + 255) / 256, 256, 0, s>>>(lats, count, chunk);
-    return hipGetLastError();
-}
 
 hipError_t launch_init(const LatDesc &d, int dst, const double *rho, const double *ux,
                        const double *uy, hipStream_t s)

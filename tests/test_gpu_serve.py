@@ -1,0 +1,62 @@
+"""The solve server on the GPU: continuous batching over the batched kernel.
+
+Each request's result in the mix must equal its result served alone
+(bitwise: the batched kernel does each node's arithmetic exactly as the
+single-lattice kernel), and a sample must match the oracle within the
+storage tolerance of the parity tests.
+"""
+import numpy as np
+import pytest
+
+from paper_1705_11092_amd import inputs
+from tests.gpu_util import e2_u, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream():
+    return inputs.served_stream(count=14, seed=7, rate=80.0, n_lo=24, n_hi=160, steps_lo=40,
+                                steps_hi=700)
+
+
+def test_served_results_equal_solo_results():
+    from paper_1705_11092_amd.serve import GpuBackend, Server, run_alone
+    reqs = _stream()
+    be = GpuBackend(budget_bytes=256 * 2**20)
+    rep = Server(be, min_tick=32, max_tick=256, tick_s=0.002).run(reqs)
+    s = rep.summary()
+    log(f"served: {s}")
+    assert s["done"] == len(reqs)
+    assert rep.max_active >= 2  # requests really overlapped
+    for req in reqs:
+        solo = run_alone(GpuBackend(budget_bytes=256 * 2**20), req)
+        got = rep.results[req.rid]
+        assert solo.status == "done"
+        assert np.array_equal(got.rho, solo.rho), req.rid
+        assert np.array_equal(got.ux, solo.ux), req.rid
+        assert np.array_equal(got.uy, solo.uy), req.rid
+
+
+def test_served_results_match_the_oracle():
+    from paper_1705_11092_amd.serve import GpuBackend, Server
+    reqs = _stream()[:6]
+    rep = Server(GpuBackend(budget_bytes=256 * 2**20), min_tick=32, max_tick=128,
+                 tick_s=0.002).run(reqs)
+    tol = {"f32": 1e-5, "f16": 3e-3, "bf16": 3e-2}
+    for req in reqs:
+        _, ro, uo, vo = oracle_run(req.workload, req.workload.steps)
+        got = rep.results[req.rid]
+        e = e2_u(got.ux, got.uy, uo, vo)
+        log(f"request {req.rid} {req.workload.name} {req.storage}: E2(u) = {e:.3e}")
+        assert e <= tol[req.storage]
+
+
+def test_admission_limit_on_gpu():
+    from paper_1705_11092_amd import clbm
+    from paper_1705_11092_amd.serve import GpuBackend, Server
+    reqs = _stream()
+    one = max(2 * clbm.buffer_bytes(r.workload.nx, r.workload.ny, r.storage) for r in reqs)
+    be = GpuBackend(budget_bytes=2 * one)
+    rep = Server(be, min_tick=32, max_tick=256, tick_s=0.002).run(reqs)
+    assert rep.peak_bytes <= 2 * one
+    assert rep.summary()["done"] == len(reqs)
