@@ -18,12 +18,6 @@
 
 using clbm::LatDesc;
 
-// Extra elements between population planes (skews the nine streams across
-// HBM channels; 0 keeps planes back to back).
-#ifndef CLBM_PLANE_PAD_ELEMS
-#define CLBM_PLANE_PAD_ELEMS 0
-#endif
-
 namespace {
 
 thread_local std::string g_err;
@@ -57,24 +51,19 @@ int elem_bytes(int storage)
     }
 }
 
+// Elements of one direction's run within a lattice row (padded).
 int64_t pitch_of(int nx) { return ((int64_t)nx + clbm::kRowAlign - 1) / clbm::kRowAlign * clbm::kRowAlign; }
-
-// Planes start on 256-byte boundaries (64 elements covers every type).
-int64_t plane_of(int nx, int ny)
-{
-    const int64_t raw = pitch_of(nx) * ny;
-    return (raw + 63) / 64 * 64 + CLBM_PLANE_PAD_ELEMS;
-}
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
 
-// Default nodes per thread of the single-lattice step: 16-byte vectors.
+// Default nodes per thread of the single-lattice step: 16-byte vectors for
+// FP64 and FP32, 8-byte vectors for 16-bit storage (fewer live registers).
 int default_vec(int storage)
 {
     switch (storage) {
     case CLBM_F64: return 2;
     case CLBM_F32: return 4;
-    default: return 8;
+    default: return 4;
     }
 }
 
@@ -217,7 +206,7 @@ size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage)
     const int eb = elem_bytes(storage);
     if (nx < 1 || ny < 1 || eb == 0) return 0;
     if (pitch_of(nx) * (int64_t)ny > (int64_t)INT32_MAX) return 0;
-    return (size_t)(9 * plane_of(nx, ny) * eb);
+    return (size_t)(9 * pitch_of(nx) * ny * eb);
 }
 
 int clbm_create(const clbm_config *cfg, clbm_handle **out)
@@ -252,10 +241,10 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     std::memset(&d, 0, sizeof d);
     d.buf[0] = cfg->pop_a;
     d.buf[1] = cfg->pop_b;
-    d.plane = plane_of(cfg->nx, cfg->ny);
+    d.dstride = pitch_of(cfg->nx);
+    d.rstride = 9 * pitch_of(cfg->nx);
     d.nx = cfg->nx;
     d.ny = cfg->ny;
-    d.pitch = (int32_t)pitch_of(cfg->nx);
     d.bc_y = cfg->bc_y;
     d.storage = cfg->storage;
     d.force_mode = clbm::FM_CONST;

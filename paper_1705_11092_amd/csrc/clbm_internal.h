@@ -16,8 +16,9 @@ enum ForceMode {
 // Threads per block of every step kernel.
 constexpr int kBlock = 256;
 
-// Row padding: each row starts on a multiple of kRowAlign elements so that
-// the vector stores of every storage type are naturally aligned.
+// Row padding: each direction's row starts on a multiple of kRowAlign
+// elements so that the vector stores of every storage type are naturally
+// aligned.
 constexpr int kRowAlign = 8;
 
 // Everything a kernel needs to step one lattice.  Passed by value to the
@@ -25,9 +26,9 @@ constexpr int kRowAlign = 8;
 struct LatDesc {
     void *buf[2];        // ping-pong population buffers
     const void *force;   // FM_ROW: table[ny]; FM_FIELD: fx plane then fy plane
-    int64_t plane;       // elements between population planes
+    int64_t dstride;     // elements between the rows of two directions
+    int64_t rstride;     // elements between two lattice rows (all 9 directions)
     int32_t nx, ny;      // lattice size
-    int32_t pitch;       // elements between rows
     int32_t bc_y;        // 0 periodic, 1 half-way bounce-back
     int32_t storage;     // StorageKind
     int32_t force_mode;  // ForceMode

@@ -8,11 +8,15 @@
 // stored value is read exactly once per step, so there is no reuse for LDS
 // to capture: the step is bound by HBM traffic, 2 x 9 values per node.
 //
-// Layout: buffer = 9 planes (direction order of Eq. 1), plane = ny rows of
-// `pitch` elements, x fastest.  Rows start on multiples of 8 elements, so a
-// thread's stores are naturally aligned vectors; the loads of the x-shifted
-// directions are offset by one element and use element-aligned vector
-// loads.
+// Layout: row-interleaved.  Lattice row y holds the 9 directions (order of
+// Eq. 1) one after the other, each a run of nx elements padded to a multiple
+// of 8, x fastest: element (i, y, x) sits at y * rstride + i * dstride + x.
+// A step therefore streams through three neighbouring row blocks of 9 runs
+// each instead of 18 separate planes, which keeps the HBM pages it touches
+// few.  Rows start on multiples of 8 elements, so a thread's stores are
+// naturally aligned vectors; the loads of the x-shifted directions are
+// offset by one element and use element-aligned vector loads.  Loads and
+// stores are non-temporal: every value is used once per step.
 #include "clbm_device.h"
 #include "clbm_internal.h"
 
@@ -41,9 +45,10 @@ __device__ __forceinline__ Pack<T, N> load_pack(const T *p)
 {
     Pack<T, N> r;
     if constexpr (N == 1) {
-        r.v[0] = *p;
+        r.v[0] = __builtin_nontemporal_load(p);
     } else {
-        const typename VecTypes<T, N>::loose v = *reinterpret_cast<const typename VecTypes<T, N>::loose *>(p);
+        const typename VecTypes<T, N>::loose v =
+            __builtin_nontemporal_load(reinterpret_cast<const typename VecTypes<T, N>::loose *>(p));
 #pragma unroll
         for (int k = 0; k < N; ++k) r.v[k] = v[k];
     }
@@ -54,12 +59,12 @@ template <typename T, int N>
 __device__ __forceinline__ void store_pack(T *p, const Pack<T, N> &v)
 {
     if constexpr (N == 1) {
-        *p = v.v[0];
+        __builtin_nontemporal_store(v.v[0], p);
     } else {
         typename VecTypes<T, N>::tight a;
 #pragma unroll
         for (int k = 0; k < N; ++k) a[k] = v.v[k];
-        *reinterpret_cast<typename VecTypes<T, N>::tight *>(p) = a;
+        __builtin_nontemporal_store(a, reinterpret_cast<typename VecTypes<T, N>::tight *>(p));
     }
 }
 
@@ -108,11 +113,11 @@ __device__ __forceinline__ void force_at(const LatDesc &d, int x, int y, R &Fx, 
     }
 }
 
-// Source of the pre-collision population i at a node of row y: the plane,
+// Source of the pre-collision population i at a node of row y: the direction,
 // row and x-offset of the post-collision value it is pulled from.  Beyond
 // a bounce-back wall the population is the node's own reversed one.
 struct Source {
-    int plane, row, dx;
+    int dir, row, dx;
 };
 
 __device__ __forceinline__ Source source_of(const LatDesc &d, int i, int y)
@@ -120,7 +125,7 @@ __device__ __forceinline__ Source source_of(const LatDesc &d, int i, int y)
     Source s{i, y - ey_of(i), ex_of(i)};
     if (s.row < 0 || s.row >= d.ny) {
         if (d.bc_y) {
-            s.plane = opp_of(i);
+            s.dir = opp_of(i);
             s.row = y;
             s.dx = 0;
         } else {
@@ -163,7 +168,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const Source s = source_of(d, i, y);
-        rowp[i] = in + (int64_t)s.plane * d.plane + (int64_t)s.row * d.pitch;
+        rowp[i] = in + (int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride;
         dxs[i] = s.dx;
     }
 
@@ -192,21 +197,21 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         collide<R, SCH>(g[k], Fx, Fy, rt);
     }
 
-    T *o = out + (int64_t)y * d.pitch + x0;
+    T *o = out + (int64_t)y * d.rstride + x0;
     if (x0 + VEC <= d.nx) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             Pack<T, VEC> p;
 #pragma unroll
             for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
-            store_pack<T, VEC>(o + (int64_t)i * d.plane, p);
+            store_pack<T, VEC>(o + (int64_t)i * d.dstride, p);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             if (x0 + k < d.nx) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) o[(int64_t)i * d.plane + k] = S::from_r(g[k][i]);
+                for (int i = 0; i < 9; ++i) o[(int64_t)i * d.dstride + k] = S::from_r(g[k][i]);
             }
         }
     }
@@ -307,7 +312,7 @@ __device__ __forceinline__ void put_pre(const LatDesc &d, int dst, int i, int x,
     using R = typename S::R;
     const Source s = source_of(d, i, y);
     T *out = static_cast<T *>(d.buf[dst]);
-    out[(int64_t)s.plane * d.plane + (int64_t)s.row * d.pitch + wrap_x(x - s.dx, d.nx)] =
+    out[(int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride + wrap_x(x - s.dx, d.nx)] =
         S::from_r(R(v));
 }
 
@@ -318,7 +323,7 @@ __device__ __forceinline__ double get_pre(const LatDesc &d, int src, int i, int 
     using T = typename S::T;
     const Source s = source_of(d, i, y);
     const T *in = static_cast<const T *>(d.buf[src]);
-    return (double)S::to_r(in[(int64_t)s.plane * d.plane + (int64_t)s.row * d.pitch +
+    return (double)S::to_r(in[(int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride +
                               wrap_x(x - s.dx, d.nx)]);
 }
 

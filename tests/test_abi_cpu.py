@@ -31,11 +31,11 @@ def test_host_helpers():
     assert clbm.nonslip_s3(1.0) == pytest.approx(8.0 / 7.0)
     assert clbm.nonslip_s3(1.754) == pytest.approx(inputs.nonslip_s3(1.754))
     assert clbm.s_from_nu(0.01) == pytest.approx(1.0 / 0.53)
-    # Buffer sizes: 9 planes, rows padded to 8 elements, planes to 64.
+    # Buffer sizes: 9 direction runs per row, each padded to 8 elements.
     assert clbm.buffer_bytes(4096, 4096, "f32") == 9 * 4096 * 4096 * 4
     assert clbm.buffer_bytes(4096, 4096, "f16") == 9 * 4096 * 4096 * 2
     assert clbm.buffer_bytes(64, 32, "f64") == 9 * 64 * 32 * 8
-    assert clbm.buffer_bytes(37, 23, "f32") == 9 * ((40 * 23 + 63) // 64 * 64) * 4
+    assert clbm.buffer_bytes(37, 23, "f32") == 9 * 40 * 23 * 4
     assert clbm.buffer_bytes(0, 5, "f32") == 0
     assert clbm.lib.clbm_buffer_bytes(5, 5, 9) == 0
 
