@@ -22,9 +22,15 @@
 //   k~22 - rho/9 = kxxyy - dr/9 - 2 ux kxyy - 2 uy kxxy + ux^2 kyy + uy^2 kxx
 //                  + (ux^2 + uy^2) rho0/3 + 4 ux uy kxy - 3 rho ux^2 uy^2
 //                  + ux uy (uy Fx + ux Fy)
-// and symmetric ones with x and y exchanged.  After relaxation the raw
-// moments are rebuilt with the inverse binomial shift (Eq. 9's N^-1) and the
-// populations with M^-1 (Appendix), again as deviations.
+// and symmetric ones with x and y exchanged.  The collision then changes
+// each central moment by Delta T~ = T~* - T~ (Eq. 12: -s (T~ - T~eq) plus the
+// force term, and exactly F in the first-order slots), and only that change
+// is carried back through N^-1(u) (the inverse binomial shift) and M^-1
+// (Appendix): g* = g + M^-1 N^-1 Delta T~.  Carrying the small change rather
+// than the whole post-collision state keeps FP32 rounding unbiased: the
+// population values are rounded once, in the final add, while the force
+// increment enters as F itself instead of as F added to rho u (whose FP32
+// rounding has the same sign at every node and step, a steady drift).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -115,28 +121,32 @@ __host__ __device__ __forceinline__ float recip(float x)
 
 // Back-transform (Eq. 9): from the post-collision central moments, given as
 // deviations, to post-collision deviations g*.
+//   mx, my   : rho ux and rho uy, passed exactly (j + F/2), so that the
+//              rebuilt first moments are c10 + mx to one rounding and
+//              momentum is conserved without a drift from rho * (mx / rho)
 //   c10, c01 : k~10*, k~01*
 //   p, q     : k~20* - rho/3 and k~02* - rho/3
 //   a5..a8   : k~11*, k~21*, k~12*, k~22* - rho/9
 template <typename R>
-__host__ __device__ __forceinline__ void from_central(R dr, R rho, R ux, R uy, R c10, R c01, R p, R q, R a5,
-                                             R a6, R a7, R a8, R g[9])
+__host__ __device__ __forceinline__ void from_central(R dr, R rho, R mx, R my, R ux, R uy, R c10, R c01,
+                                                      R p, R q, R a5, R a6, R a7, R a8, R g[9])
 {
     const R third = R(1) / R(3);
     const R ninth = R(1) / R(9);
     const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
     const R c20 = rho * third + p;  // full k~20*
     const R c02 = rho * third + q;  // full k~02*
-    // Raw moments (inverse binomial shift) minus the rest-state raw moments.
-    const R r10 = c10 + rho * ux;
-    const R r01 = c01 + rho * uy;
-    const R r20 = dr * third + p + R(2) * ux * c10 + rho * uxx;
-    const R r02 = dr * third + q + R(2) * uy * c01 + rho * uyy;
-    const R r11 = a5 + ux * c01 + uy * c10 + rho * uxy;
-    const R r21 = a6 + R(2) * ux * a5 + uy * c20 + uxx * c01 + R(2) * uxy * c10 + rho * uxx * uy;
-    const R r12 = a7 + R(2) * uy * a5 + ux * c02 + uyy * c10 + R(2) * uxy * c01 + rho * ux * uyy;
+    // Raw moments (inverse binomial shift) minus the rest-state raw moments;
+    // rho u^a u^b is written (rho ux) ux... from the exact momentum.
+    const R r10 = c10 + mx;
+    const R r01 = c01 + my;
+    const R r20 = dr * third + p + R(2) * ux * c10 + mx * ux;
+    const R r02 = dr * third + q + R(2) * uy * c01 + my * uy;
+    const R r11 = a5 + ux * c01 + uy * c10 + mx * uy;
+    const R r21 = a6 + R(2) * ux * a5 + uy * c20 + uxx * c01 + R(2) * uxy * c10 + mx * uxy;
+    const R r12 = a7 + R(2) * uy * a5 + ux * c02 + uyy * c10 + R(2) * uxy * c01 + my * uxy;
     const R r22 = dr * ninth + a8 + R(2) * ux * a7 + R(2) * uy * a6 + uxx * c02 + uyy * c20 +
-                  R(4) * uxy * a5 + R(2) * ux * uyy * c10 + R(2) * uxx * uy * c01 + rho * uxx * uyy;
+                  R(4) * uxy * a5 + R(2) * ux * uyy * c10 + R(2) * uxx * uy * c01 + mx * ux * uyy;
     // M^-1 (Appendix), row by row.
     const R h = R(0.5), qr = R(0.25);
     g[0] = dr - (r20 + r02) + r22;
@@ -148,6 +158,36 @@ __host__ __device__ __forceinline__ void from_central(R dr, R rho, R ux, R uy, R
     g[6] = qr * (-r11 + r21 - r12 + r22);
     g[7] = qr * (r11 - r21 - r12 + r22);
     g[8] = qr * (-r11 - r21 + r12 + r22);
+}
+
+// Change of the raw-moment deviations and populations for a change D of the
+// central moments about u (Eq. 9 applied to D, D0 = 0):
+//   d10, d01 : D k~10, D k~01
+//   d20, d02 : D k~20, D k~02
+//   d11..d22 : D k~11, D k~21, D k~12, D k~22
+// dg receives M^-1 N^-1(u) D.
+template <typename R>
+__host__ __device__ __forceinline__ void delta_back(R ux, R uy, R d10, R d01, R d20, R d02, R d11,
+                                                    R d21, R d12, R d22, R dg[9])
+{
+    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    const R r20 = d20 + R(2) * ux * d10;
+    const R r02 = d02 + R(2) * uy * d01;
+    const R r11 = d11 + ux * d01 + uy * d10;
+    const R r21 = d21 + R(2) * ux * d11 + uy * d20 + uxx * d01 + R(2) * uxy * d10;
+    const R r12 = d12 + R(2) * uy * d11 + ux * d02 + uyy * d10 + R(2) * uxy * d01;
+    const R r22 = d22 + R(2) * ux * d12 + R(2) * uy * d21 + uxx * d02 + uyy * d20 + R(4) * uxy * d11 +
+                  R(2) * ux * uyy * d10 + R(2) * uxx * uy * d01;
+    const R h = R(0.5), qr = R(0.25);
+    dg[0] = r22 - (r20 + r02);
+    dg[1] = h * (d10 + r20 - r12 - r22);
+    dg[2] = h * (d01 + r02 - r21 - r22);
+    dg[3] = h * (-d10 + r20 + r12 - r22);
+    dg[4] = h * (-d01 + r02 + r21 - r22);
+    dg[5] = qr * (r11 + r21 + r12 + r22);
+    dg[6] = qr * (-r11 + r21 - r12 + r22);
+    dg[7] = qr * (r11 - r21 - r12 + r22);
+    dg[8] = qr * (-r11 - r21 + r12 + r22);
 }
 
 // One collision in place: g holds pre-collision deviations on entry and
@@ -168,8 +208,10 @@ __host__ __device__ __forceinline__ void collide(R g[9], R Fx, R Fy, const Rates
     const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     const R rho = rt.rho0 + dr;
     const R inv = recip(rho);
-    const R ux = (jx + h * Fx) * inv;
-    const R uy = (jy + h * Fy) * inv;
+    const R mx = jx + h * Fx;  // rho ux (Eq. 15)
+    const R my = jy + h * Fy;
+    const R ux = mx * inv;
+    const R uy = my * inv;
 
     // Raw moments of g above first order.
     const R kxx = sx + sd;
@@ -182,43 +224,46 @@ __host__ __device__ __forceinline__ void collide(R g[9], R Fx, R Fy, const Rates
     // Central moments as deviations from T~eq (Eq. 8).
     const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
     const R r3 = rt.rho0 * third;
-    const R cxx = kxx - dr * third - rho * uxx + ux * Fx;
-    const R cyy = kyy - dr * third - rho * uyy + uy * Fy;
-    const R cxy = kxy - rho * uxy + h * (ux * Fy + uy * Fx);
-    const R cxxy = kxxy - R(2) * ux * kxy - uy * (kxx + r3) + R(2) * rho * uxx * uy - h * uxx * Fy -
+    const R cxx = kxx - dr * third - mx * ux + ux * Fx;
+    const R cyy = kyy - dr * third - my * uy + uy * Fy;
+    const R cxy = kxy - mx * uy + h * (ux * Fy + uy * Fx);
+    const R cxxy = kxxy - R(2) * ux * kxy - uy * (kxx + r3) + R(2) * mx * uxy - h * uxx * Fy -
                    uxy * Fx;
-    const R cxyy = kxyy - R(2) * uy * kxy - ux * (kyy + r3) + R(2) * rho * ux * uyy - h * uyy * Fx -
+    const R cxyy = kxyy - R(2) * uy * kxy - ux * (kyy + r3) + R(2) * my * uxy - h * uyy * Fx -
                    uxy * Fy;
     const R cxxyy = kxxyy - dr * ninth - R(2) * ux * kxyy - R(2) * uy * kxxy + uxx * kyy + uyy * kxx +
-                    (uxx + uyy) * r3 + R(4) * uxy * kxy - R(3) * rho * uxx * uyy +
+                    (uxx + uyy) * r3 + R(4) * uxy * kxy - R(3) * mx * ux * uyy +
                     uxy * (uy * Fx + ux * Fy);
 
-    // Relaxation, Eq. (12) (or Eq. 21), slot by slot.
-    const R a3 = rt.omb * (cxx + cyy);
-    const R a4 = rt.om2 * (cxx - cyy);
-    const R a5 = rt.om2 * cxy;
-    R a6 = rt.om3 * cxxy;
-    R a7 = rt.om3 * cxyy;
-    R a8 = rt.om4 * cxxyy;
-    R c10, c01;
+    // Change of each central moment, Eq. (12) (or Eq. 21): the relaxation
+    // -s (T~ - T~eq) = (1 - s - 1) (...) and the force term.
+    const R D3 = (rt.omb - R(1)) * (cxx + cyy);
+    const R D4 = (rt.om2 - R(1)) * (cxx - cyy);
+    const R D5 = (rt.om2 - R(1)) * cxy;
+    R D6 = (rt.om3 - R(1)) * cxxy;
+    R D7 = (rt.om3 - R(1)) * cxyy;
+    R D8 = (rt.om4 - R(1)) * cxxyy;
+    R D1, D2;
     if (SCH == SCH_CONSISTENT) {
         // Eq. (14): C = [0, Fx, Fy, 0, 0, 0, Fy/3, Fx/3, 0].  The first-order
-        // slots come out at +F/2 whatever s1 is.
-        c10 = h * Fx;
-        c01 = h * Fy;
-        a6 += rt.h3 * (third * Fy);
-        a7 += rt.h3 * (third * Fx);
+        // central moments go from -F/2 to +F/2 whatever s1 is.
+        D1 = Fx;
+        D2 = Fy;
+        D6 += rt.h3 * (third * Fy);
+        D7 += rt.h3 * (third * Fx);
     } else {
-        // Eq. (21): central moments of Guo's term, weighted by 1 - s2/2.
-        c10 = -h * rt.om1 * Fx + rt.h2 * Fx;
-        c01 = -h * rt.om1 * Fy + rt.h2 * Fy;
-        a6 += rt.h2 * (third * Fy - R(2) * uxy * Fx - uxx * Fy);
-        a7 += rt.h2 * (third * Fx - uyy * Fx - R(2) * uxy * Fy);
-        a8 += rt.h2 * (R(4) * uxy * (uy * Fx + ux * Fy));
+        // Eq. (21): central moments of Guo's term, weighted by 1 - s2/2; the
+        // first-order slots relax at s1 from -F/2.
+        D1 = h * (R(1) - rt.om1) * Fx + rt.h2 * Fx;
+        D2 = h * (R(1) - rt.om1) * Fy + rt.h2 * Fy;
+        D6 += rt.h2 * (third * Fy - R(2) * uxy * Fx - uxx * Fy);
+        D7 += rt.h2 * (third * Fx - uyy * Fx - R(2) * uxy * Fy);
+        D8 += rt.h2 * (R(4) * uxy * (uy * Fx + ux * Fy));
     }
-    const R p = h * (a3 + a4);
-    const R q = h * (a3 - a4);
-    from_central<R>(dr, rho, ux, uy, c10, c01, p, q, a5, a6, a7, a8, g);
+    R dg[9];
+    delta_back<R>(ux, uy, D1, D2, h * (D3 + D4), h * (D3 - D4), D5, D6, D7, D8, dg);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] += dg[i];
 }
 
 // Pre-collision deviations of the start state (central moments
@@ -227,7 +272,8 @@ template <typename R>
 __host__ __device__ __forceinline__ void start_state(R rho0, R rho, R ux, R uy, R Fx, R Fy, R g[9])
 {
     const R h = R(0.5);
-    from_central<R>(rho - rho0, rho, ux, uy, -h * Fx, -h * Fy, R(0), R(0), R(0), R(0), R(0), R(0), g);
+    from_central<R>(rho - rho0, rho, rho * ux, rho * uy, ux, uy, -h * Fx, -h * Fy, R(0), R(0), R(0),
+                    R(0), R(0), R(0), g);
 }
 
 }  // namespace clbm
