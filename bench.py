@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-BYTES_PER_LUP = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}
+BYTES_PER_LUP = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36, "f16sr": 36, "bf16sr": 36}
 KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_kernels.hip",
                   "paper_1705_11092_amd/csrc/clbm_device.h",
                   "paper_1705_11092_amd/csrc/clbm_internal.h"]
@@ -227,7 +227,7 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        for st in ("f16", "bf16"):
+        for st in ("f16", "bf16", "f16sr", "bf16sr"):
             ms16, _, _ = run_gpu(args.n, st, args.steps, args.warmup)
             m = nodes / (ms16 / args.steps / 1e3) / 1e6
             extra[st] = {"mlups": round(m, 1), "ms_per_step": round(ms16 / args.steps, 5),

@@ -53,12 +53,19 @@ extern "C" {
 
 /* Storage of the populations.  Every type stores the deviation
  * f_i - w_i rho0 from the rest equilibrium w_i rho0 (w = 4/9, 1/9 x4,
- * 1/36 x4).  CLBM_F64 computes in FP64; the others compute in FP32. */
+ * 1/36 x4).  CLBM_F64 computes in FP64; the others compute in FP32.  The
+ * _SR types round each stored value stochastically (to the lower or upper
+ * 16-bit neighbour with the probabilities that make the rounding exact on
+ * average), from a deterministic hash of the node index and the node's
+ * values: no systematic drift when the state moves by a few ulps per step,
+ * and bitwise the same results for a lattice alone or in a batch. */
 typedef enum {
     CLBM_F64 = 0,
     CLBM_F32 = 1,
-    CLBM_F16 = 2,  /* IEEE binary16, round to nearest even */
-    CLBM_BF16 = 3  /* bfloat16, round to nearest even      */
+    CLBM_F16 = 2,    /* IEEE binary16, round to nearest even */
+    CLBM_BF16 = 3,   /* bfloat16, round to nearest even      */
+    CLBM_F16_SR = 4, /* IEEE binary16, stochastic rounding   */
+    CLBM_BF16_SR = 5 /* bfloat16, stochastic rounding        */
 } clbm_storage;
 
 /* Boundary in y (x is always periodic), Sec. IV A. */

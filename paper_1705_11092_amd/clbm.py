@@ -16,8 +16,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libclbm.so")
 
-STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
-ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f16sr": 4, "bf16sr": 5}
+ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16sr": 2, "bf16sr": 2}
 BC = {"periodic": 0, "bounceback": 1}
 FORCE = {"none": 0, "const": 1, "kolmogorov": 2, "field": 3}
 SCHEME = {"consistent": 0, "guo_lbl": 1}

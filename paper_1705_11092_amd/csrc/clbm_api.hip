@@ -46,13 +46,17 @@ int elem_bytes(int storage)
     case CLBM_F64: return 8;
     case CLBM_F32: return 4;
     case CLBM_F16:
-    case CLBM_BF16: return 2;
+    case CLBM_BF16:
+    case CLBM_F16_SR:
+    case CLBM_BF16_SR: return 2;
     default: return 0;
     }
 }
 
 // Elements of one direction's run within a lattice row (padded).
 int64_t pitch_of(int nx) { return ((int64_t)nx + clbm::kRowAlign - 1) / clbm::kRowAlign * clbm::kRowAlign; }
+
+constexpr int kStorageKinds = 6;
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
 
@@ -647,14 +651,14 @@ std::string batch_signature(const clbm_batch *b)
         arch = prop.gcnArchName;
     for (char &c : arch)
         if (c == ' ' || c == ':') c = '_';
-    int64_t nodes[4] = {0, 0, 0, 0}, counts[4] = {0, 0, 0, 0};
+    int64_t nodes[kStorageKinds] = {}, counts[kStorageKinds] = {};
     for (auto *h : b->lats) {
         nodes[h->d.storage] += (int64_t)h->d.nx * h->d.ny;
         counts[h->d.storage] += 1;
     }
     std::ostringstream os;
     os << arch;
-    for (int st = 0; st < 4; ++st) {
+    for (int st = 0; st < kStorageKinds; ++st) {
         // Shape class: lattice count and log2 of the node total per storage.
         int lg = 0;
         while (nodes[st] >> (lg + 1)) ++lg;
@@ -682,7 +686,7 @@ int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream,
     clbm_batch *b = new clbm_batch();
     b->lats = v;
     b->stream = static_cast<hipStream_t>(stream);
-    for (int st = 0; st < 4; ++st)
+    for (int st = 0; st < kStorageKinds; ++st)
         for (int j = 0; j < count; ++j)
             if (v[j]->d.storage == st) b->order.push_back(j);
     int dev = 0;

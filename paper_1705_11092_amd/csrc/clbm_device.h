@@ -54,13 +54,14 @@ __device__ __forceinline__ R weight(int i)
 
 // ---- storage conversions ---------------------------------------------------
 
-enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum StorageKind { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F16_SR = 4, ST_BF16_SR = 5 };
 
 template <int ST> struct Storage;
 
 template <> struct Storage<ST_F64> {
     using T = double;  // stored element
     using R = double;  // arithmetic
+    static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return v; }
     static __device__ __forceinline__ T from_r(R v) { return v; }
 };
@@ -68,6 +69,7 @@ template <> struct Storage<ST_F64> {
 template <> struct Storage<ST_F32> {
     using T = float;
     using R = float;
+    static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return v; }
     static __device__ __forceinline__ T from_r(R v) { return v; }
 };
@@ -75,6 +77,7 @@ template <> struct Storage<ST_F32> {
 template <> struct Storage<ST_F16> {
     using T = _Float16;
     using R = float;
+    static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
     static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }  // RNE
 };
@@ -84,9 +87,67 @@ template <> struct Storage<ST_F16> {
 template <> struct Storage<ST_BF16> {
     using T = __bf16;
     using R = float;
+    static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
     static __device__ __forceinline__ T from_r(R v) { return (__bf16)v; }
 };
+
+// Stochastically rounded 16-bit storage.  A value that changes by a few
+// units in the last place per step (a slowly evolving flow, a small body
+// force) is rounded the same way step after step by round-to-nearest, a
+// drift that accumulates.  Here each stored value v is rounded to nearest
+// after adding a uniform dither of one 16-bit ulp, r - 1/2 with r in
+// [0, 1): the result is the lower or upper neighbour of v with
+// probabilities that make it exact on average.  r comes from a hash of the
+// node index and the node's own FP32 values, so it is deterministic (a
+// lattice gives the same bits alone or in any batch, in any launch shape)
+// and changes from step to step with the state.
+template <> struct Storage<ST_F16_SR> {
+    using T = _Float16;
+    using R = float;
+    static constexpr bool kDither = true;
+    // ulp = 2^(e - 11) for v = m 2^e, m in [0.5, 1), down to the
+    // binary16 subnormal spacing 2^-24.
+    static constexpr int kUlpShift = 11;
+    static constexpr int kUlpMin = -24;
+    static __device__ __forceinline__ R to_r(T v) { return (float)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }
+};
+
+template <> struct Storage<ST_BF16_SR> {
+    using T = __bf16;
+    using R = float;
+    static constexpr bool kDither = true;
+    static constexpr int kUlpShift = 8;
+    static constexpr int kUlpMin = -126;
+    static __device__ __forceinline__ R to_r(T v) { return (float)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (__bf16)v; }
+};
+
+// 32-bit integer finaliser (xor-shift-multiply, as in MurmurHash3's fmix32
+// structure with different constants).
+__device__ __forceinline__ uint32_t hash32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+// v plus a dither of (r - 1/2) ulp, r from 24 bits of (h * odd_i); zero
+// stays zero.  The caller rounds the result to nearest.
+template <typename S>
+__device__ __forceinline__ float dithered(float v, uint32_t h, int i)
+{
+    const uint32_t r = (h * (2u * (uint32_t)i + 0x2545f491u)) >> 8;
+    int e = __builtin_amdgcn_frexp_expf(v) - S::kUlpShift;
+    e = e < S::kUlpMin ? S::kUlpMin : e;
+    const float ulp = __uint_as_float((uint32_t)(e + 127) << 23);
+    const float d = ((float)r * (1.0f / 16777216.0f) - 0.5f) * ulp;
+    return v != 0.0f ? v + d : v;
+}
 
 // ---- relaxation parameters in the arithmetic type --------------------------
 

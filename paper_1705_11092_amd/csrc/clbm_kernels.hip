@@ -197,6 +197,16 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         collide<R, SCH>(g[k], Fx, Fy, rt);
     }
 
+    if constexpr (S::kDither) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + k);
+            const uint32_t h = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[k][i] = dithered<S>(g[k][i], h, i);
+        }
+    }
+
     T *o = out + (int64_t)y * d.rstride + x0;
     if (x0 + VEC <= d.nx) {
 #pragma unroll
@@ -558,6 +568,14 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s)
         return vec == 2   ? step_dispatch<ST_BF16, 2>(d, src, s)
                : vec == 4 ? step_dispatch<ST_BF16, 4>(d, src, s)
                           : step_dispatch<ST_BF16, 8>(d, src, s);
+    case ST_F16_SR:
+        return vec == 2   ? step_dispatch<ST_F16_SR, 2>(d, src, s)
+               : vec == 4 ? step_dispatch<ST_F16_SR, 4>(d, src, s)
+                          : step_dispatch<ST_F16_SR, 8>(d, src, s);
+    case ST_BF16_SR:
+        return vec == 2   ? step_dispatch<ST_BF16_SR, 2>(d, src, s)
+               : vec == 4 ? step_dispatch<ST_BF16_SR, 4>(d, src, s)
+                          : step_dispatch<ST_BF16_SR, 8>(d, src, s);
     default:
         return hipErrorInvalidValue;
     }
@@ -576,6 +594,10 @@ hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles,
         return vec == 2 ? CLBM_B(ST_F16, 2) : vec == 4 ? CLBM_B(ST_F16, 4) : CLBM_B(ST_F16, 8);
     case ST_BF16:
         return vec == 2 ? CLBM_B(ST_BF16, 2) : vec == 4 ? CLBM_B(ST_BF16, 4) : CLBM_B(ST_BF16, 8);
+    case ST_F16_SR:
+        return vec == 2 ? CLBM_B(ST_F16_SR, 2) : vec == 4 ? CLBM_B(ST_F16_SR, 4) : CLBM_B(ST_F16_SR, 8);
+    case ST_BF16_SR:
+        return vec == 2 ? CLBM_B(ST_BF16_SR, 2) : vec == 4 ? CLBM_B(ST_BF16_SR, 4) : CLBM_B(ST_BF16_SR, 8);
     default:
         return hipErrorInvalidValue;
     }
@@ -600,6 +622,8 @@ hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t
     case ST_F32: KERNEL<ST_F32><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;               \
     case ST_F16: KERNEL<ST_F16><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;               \
     case ST_BF16: KERNEL<ST_BF16><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;             \
+    case ST_F16_SR: KERNEL<ST_F16_SR><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;         \
+    case ST_BF16_SR: KERNEL<ST_BF16_SR><<<GRID, kBlock, 0, s>>>(__VA_ARGS__); break;       \
     default: return hipErrorInvalidValue;                                                    \
     }
 

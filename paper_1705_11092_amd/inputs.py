@@ -152,11 +152,12 @@ class Request:
 
 def served_stream(count: int = 400, seed: int = 1, rate: float = 4.8,
                   n_lo: int = 64, n_hi: int = 2048, steps_lo: float = 1e3,
-                  steps_hi: float = 1e5, storage_16: str = "f16") -> List[Request]:
+                  steps_hi: float = 1e5, storage_16: str = "f16sr") -> List[Request]:
     """Poisson arrivals of solves with sides log-uniform in [n_lo, n_hi], step
     counts log-uniform in [steps_lo, steps_hi], forcing uniform over
     {constant, Kolmogorov, none} (none = decaying Taylor-Green), storage FP32
-    or 16-bit with equal odds, tau ~ U(0.55, 1.5)."""
+    or 16-bit with equal odds (FP16 with stochastic rounding unless told
+    otherwise: the more accurate 16-bit form on long runs), tau ~ U(0.55, 1.5)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []

@@ -34,10 +34,12 @@ def test_host_helpers():
     # Buffer sizes: 9 direction runs per row, each padded to 8 elements.
     assert clbm.buffer_bytes(4096, 4096, "f32") == 9 * 4096 * 4096 * 4
     assert clbm.buffer_bytes(4096, 4096, "f16") == 9 * 4096 * 4096 * 2
+    assert clbm.buffer_bytes(4096, 4096, "bf16sr") == 9 * 4096 * 4096 * 2
     assert clbm.buffer_bytes(64, 32, "f64") == 9 * 64 * 32 * 8
     assert clbm.buffer_bytes(37, 23, "f32") == 9 * 40 * 23 * 4
     assert clbm.buffer_bytes(0, 5, "f32") == 0
     assert clbm.lib.clbm_buffer_bytes(5, 5, 9) == 0
+    assert clbm.lib.clbm_buffer_bytes(5, 5, 6) == 0
 
 
 def test_create_rejects_bad_arguments_before_touching_the_gpu():

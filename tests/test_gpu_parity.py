@@ -8,6 +8,9 @@ inputs:
   FP32 deviations, FP32 math   1e-5
   FP16 deviations, FP32 math   3e-3   (measured, see the 16-bit tests)
   BF16 deviations, FP32 math   3e-2   (measured, see the 16-bit tests)
+  FP16 / BF16 with stochastic rounding: 1e-2 / 4e-2 (measured; over a
+  dozen steps the unbiased rounding is a little noisier than round to
+  nearest, its gain is over long runs, see the long-run tests)
 """
 import numpy as np
 import pytest
@@ -18,9 +21,9 @@ from tests.gpu_util import e2_u, gpu_lattice, gpu_run, log, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 3e-3, "bf16": 3e-2}
+TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 3e-3, "bf16": 3e-2, "f16sr": 1e-2, "bf16sr": 4e-2}
 # Relative mass difference after the start state is rounded to storage.
-TOL_MASS = {"f64": 1e-14, "f32": 1e-7, "f16": 1e-6, "bf16": 1e-5}
+TOL_MASS = {"f64": 1e-14, "f32": 1e-7, "f16": 1e-6, "bf16": 1e-5, "f16sr": 1e-6, "bf16sr": 1e-5}
 
 # (nx, ny, bc_y, force): several tiles, ragged tails, degenerate widths.
 CASES = [
@@ -47,7 +50,7 @@ def _case(nx, ny, bc, force, seed):
     return inputs.random_state(nx, ny, seed=seed, bc_y=bc, force=force, amp_f=1e-3)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "f16sr", "bf16sr"])
 @pytest.mark.parametrize("ci", range(len(CASES)))
 def test_random_state_matches_oracle(storage, ci):
     nx, ny, bc, force = CASES[ci]
@@ -105,7 +108,7 @@ def test_taylor_green_1024_graph_path(storage):
     assert rel_l2(rg, ro) <= TOL_U[storage]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16sr", "bf16sr"])
 def test_taylor_green_4096_full_size(storage):
     # The 4096^2 workload at full size in the bench's launch configuration,
     # two steps, every node compared.
@@ -132,8 +135,10 @@ def test_batch_is_bitwise_equal_to_single():
         (_case(64, 33, 1, "field", 304), "bf16"),
         (_case(96, 96, 0, "none", 305), "f64"),
         (inputs.kolmogorov(211, 5e-6, 2, 0.7), "f32"),
+        (_case(70, 45, 0, "const", 306), "f16sr"),
+        (_case(33, 90, 1, "kolmogorov", 307), "bf16sr"),
     ]
-    steps = [40, 37, 40, 5, 0, 71]
+    steps = [40, 37, 40, 5, 0, 71, 44, 39]
     ref = []
     for (wl, st), n in zip(wls, steps):
         lat = gpu_lattice(wl, st)
@@ -176,7 +181,7 @@ def test_batch_step_and_autotune_keep_results(tmp_path):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "f16sr", "bf16sr"])
 def test_every_slot_written_each_step(storage):
     # NaN-poison the destination buffer before each step: afterwards no NaN
     # may remain in the state.
@@ -193,7 +198,7 @@ def test_every_slot_written_each_step(storage):
     lat.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16sr"])
 def test_checkpoint_resume(storage):
     wl = _case(77, 41, 1, "field", 500)
     a = gpu_lattice(wl, storage)

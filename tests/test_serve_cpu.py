@@ -38,7 +38,7 @@ class FakeSlot:
 
 
 class FakeBackend:
-    BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+    BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16sr": 2, "bf16sr": 2}
 
     def __init__(self, clock, capacity, rate=1e6):
         self.clock = clock
@@ -194,6 +194,6 @@ def test_served_stream_recipe_is_seeded_and_in_range():
     for r in a:
         assert 64 <= r.workload.nx <= 2048 and r.workload.nx == r.workload.ny
         assert 1000 <= r.workload.steps <= 100000
-        assert r.storage in ("f32", "f16")
+        assert r.storage in ("f32", "f16sr")
     arr = np.array([r.arrival for r in a])
     assert np.all(np.diff(arr) > 0)
