@@ -175,7 +175,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--storage", default="f32", choices=list(BYTES_PER_LUP))
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -505,12 +505,13 @@ int vec_for(int storage, int vec_bytes)
 
 struct clbm_batch {
     std::vector<clbm_handle *> lats;  // caller's order
-    std::vector<int> order;           // table position -> caller index (grouped by storage)
+    std::vector<int> order;           // table position -> caller index (grouped by kind)
+    std::vector<int> keys;            // group key of each lattice when ordered
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;        // capture-only stream, created on first graph
     LatDesc *d_lats = nullptr;        // device lattice table (stream-ordered)
     struct Group {
-        int storage, vec, l_lo, l_hi;
+        int storage, mode, vec, l_lo, l_hi;  // mode = force_mode * 2 + scheme
         int64_t ntiles;
     };
     std::vector<Group> groups;
@@ -523,19 +524,36 @@ struct clbm_batch {
 
 namespace {
 
+// Launch group of a lattice: storage type and (force mode, scheme).
+int group_key(const LatDesc &d) { return d.storage * 8 + d.force_mode * 2 + d.scheme; }
+
+// Table order: grouped by storage, force mode and scheme (one launch per
+// group), caller order inside a group.
+void batch_order(clbm_batch *b)
+{
+    b->order.clear();
+    b->keys.clear();
+    for (int key = 0; key < kStorageKinds * 8; ++key)
+        for (size_t j = 0; j < b->lats.size(); ++j)
+            if (group_key(b->lats[j]->d) == key) b->order.push_back((int)j);
+    for (auto *h : b->lats) b->keys.push_back(group_key(h->d));
+}
+
 // Geometry of the current variant: per lattice nodes per thread, tile
-// shape and first tile; per storage group its lattice range and tile count.
+// shape and first tile; per group its lattice range and tile count.
 void batch_geometry(clbm_batch *b)
 {
     b->groups.clear();
     b->tab.assign(b->order.size(), LatDesc());
     size_t pos = 0;
     while (pos < b->order.size()) {
-        const int st = b->lats[b->order[pos]]->d.storage;
+        const LatDesc &d0 = b->lats[b->order[pos]]->d;
+        const int key = group_key(d0);
+        const int st = d0.storage;
         const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
         const int lo = (int)pos;
         int64_t tiles = 0;
-        while (pos < b->order.size() && b->lats[b->order[pos]]->d.storage == st) {
+        while (pos < b->order.size() && group_key(b->lats[b->order[pos]]->d) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
             clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.rows, &d.segs, &d.ntiles);
             d.vec = vec;
@@ -544,7 +562,7 @@ void batch_geometry(clbm_batch *b)
             b->tab[pos] = d;
             ++pos;
         }
-        b->groups.push_back({st, vec, lo, (int)pos, tiles});
+        b->groups.push_back({st, d0.force_mode * 2 + d0.scheme, vec, lo, (int)pos, tiles});
     }
     retire_graph(b->graph, b->stream);
     b->graph = nullptr;
@@ -578,12 +596,25 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps)
     return CLBM_OK;
 }
 
+// A force change since the last call can move a lattice to another kernel
+// (force mode): regroup before launching.
+void batch_refresh(clbm_batch *b)
+{
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+        if (group_key(b->lats[j]->d) != b->keys[j]) {
+            batch_order(b);
+            batch_geometry(b);
+            return;
+        }
+    }
+}
+
 int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
 {
     const int64_t grid = (int64_t)b->cus * kVariants[b->variant].blocks_per_cu;
     for (const auto &g : b->groups) {
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
-        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.vec, gg,
+        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.mode, g.vec, gg,
                                   substep, s));
     }
     return CLBM_OK;
@@ -622,6 +653,7 @@ int batch_run(clbm_batch *b, const int64_t *nsteps)
     for (auto *h : b->lats)
         if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
     if (maxn == 0) return CLBM_OK;
+    batch_refresh(b);
     int rc = batch_upload(b, nsteps);
     if (rc) return rc;
     int64_t left = maxn;
@@ -686,9 +718,7 @@ int clbm_batch_create(clbm_handle *const *lattices, int32_t count, void *stream,
     clbm_batch *b = new clbm_batch();
     b->lats = v;
     b->stream = static_cast<hipStream_t>(stream);
-    for (int st = 0; st < kStorageKinds; ++st)
-        for (int j = 0; j < count; ++j)
-            if (v[j]->d.storage == st) b->order.push_back(j);
+    batch_order(b);
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -740,6 +770,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     if (!b) return fail(CLBM_EINVAL, "batch is NULL");
     for (auto *h : b->lats)
         if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
+    batch_refresh(b);
     const std::string sig = batch_signature(b);
     if (cache_path) {
         std::ifstream in(cache_path);

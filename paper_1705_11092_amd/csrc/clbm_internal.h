@@ -69,9 +69,10 @@ inline void tile_geometry(int nx, int ny, int vec, int32_t *tpr, int32_t *rows, 
 // Launchers (clbm_kernels.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s);
 // One time step of lattices [l_lo, l_hi) of a batch table (all of one
-// storage type, tiles numbered consecutively through their tile0 fields).
+// storage type and one mode = force_mode * 2 + scheme, tiles numbered
+// consecutively through their tile0 fields).
 hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
-                        int vec, int grid, int substep, hipStream_t s);
+                        int mode, int vec, int grid, int substep, hipStream_t s);
 // Write n <= kUploadMax descriptors to lats[first..first+n) on the stream.
 hipError_t launch_upload(LatDesc *lats, int first, int n, const UploadPayload &p, hipStream_t s);
 hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s);

@@ -241,8 +241,10 @@ __global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t nti
 // `substep`.  Persistent: block b takes one contiguous chunk of the tile
 // range of lattices [l_lo, l_hi) (numbered lattice by lattice, row group by
 // row group), so a block walks down the rows of one lattice and on to the
-// next.
-template <int ST, int VEC>
+// next.  The lattices of one launch share storage, force mode and scheme,
+// so the kernel holds a single copy of the node update (and the register
+// budget of the single-lattice kernel).
+template <int ST, int VEC, int FM, int SCH>
 __global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats, int l_lo,
                                                   int l_hi, int64_t ntiles, int substep)
 {
@@ -267,26 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ la
         const int src = (d.parity + substep) & 1;
         int y, x0;
         if (!decode(d, t - d.tile0, threadIdx.x, y, x0)) continue;
-        switch (d.force_mode * 2 + d.scheme) {
-        case FM_CONST * 2 + SCH_CONSISTENT:
-            step_group<ST, VEC, FM_CONST, SCH_CONSISTENT>(d, src, y, x0);
-            break;
-        case FM_ROW * 2 + SCH_CONSISTENT:
-            step_group<ST, VEC, FM_ROW, SCH_CONSISTENT>(d, src, y, x0);
-            break;
-        case FM_FIELD * 2 + SCH_CONSISTENT:
-            step_group<ST, VEC, FM_FIELD, SCH_CONSISTENT>(d, src, y, x0);
-            break;
-        case FM_CONST * 2 + SCH_GUO_LBL:
-            step_group<ST, VEC, FM_CONST, SCH_GUO_LBL>(d, src, y, x0);
-            break;
-        case FM_ROW * 2 + SCH_GUO_LBL:
-            step_group<ST, VEC, FM_ROW, SCH_GUO_LBL>(d, src, y, x0);
-            break;
-        default:
-            step_group<ST, VEC, FM_FIELD, SCH_GUO_LBL>(d, src, y, x0);
-            break;
-        }
+        step_group<ST, VEC, FM, SCH>(d, src, y, x0);
     }
 }
 
@@ -541,9 +524,31 @@ hipError_t step_dispatch(const LatDesc &d, int src, hipStream_t s)
 
 template <int ST, int VEC>
 hipError_t batch_dispatch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int grid,
-                          int substep, hipStream_t s)
+                          int substep, int mode, hipStream_t s)
 {
-    k_batch<ST, VEC><<<dim3((unsigned)grid), dim3(kBlock), 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+    const dim3 g((unsigned)grid), b(kBlock);
+    switch (mode) {
+    case FM_CONST * 2 + SCH_CONSISTENT:
+        k_batch<ST, VEC, FM_CONST, SCH_CONSISTENT><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    case FM_ROW * 2 + SCH_CONSISTENT:
+        k_batch<ST, VEC, FM_ROW, SCH_CONSISTENT><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    case FM_FIELD * 2 + SCH_CONSISTENT:
+        k_batch<ST, VEC, FM_FIELD, SCH_CONSISTENT><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    case FM_CONST * 2 + SCH_GUO_LBL:
+        k_batch<ST, VEC, FM_CONST, SCH_GUO_LBL><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    case FM_ROW * 2 + SCH_GUO_LBL:
+        k_batch<ST, VEC, FM_ROW, SCH_GUO_LBL><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    case FM_FIELD * 2 + SCH_GUO_LBL:
+        k_batch<ST, VEC, FM_FIELD, SCH_GUO_LBL><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -582,9 +587,9 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s)
 }
 
 hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
-                        int vec, int grid, int substep, hipStream_t s)
+                        int mode, int vec, int grid, int substep, hipStream_t s)
 {
-#define CLBM_B(ST, V) batch_dispatch<ST, V>(lats, l_lo, l_hi, ntiles, grid, substep, s)
+#define CLBM_B(ST, V) batch_dispatch<ST, V>(lats, l_lo, l_hi, ntiles, grid, substep, mode, s)
     switch (storage) {
     case ST_F64:
         return vec == 1 ? CLBM_B(ST_F64, 1) : CLBM_B(ST_F64, 2);

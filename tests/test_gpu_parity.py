@@ -159,6 +159,28 @@ def test_batch_is_bitwise_equal_to_single():
             lat.close()
 
 
+def test_batch_follows_a_force_change():
+    # A lattice switching force mode between batch calls moves to another
+    # kernel; its result must equal a solo run with the same force history.
+    from paper_1705_11092_amd import clbm
+    wa, wb = _case(64, 40, 0, "const", 801), _case(50, 30, 1, "field", 802)
+    solo = gpu_lattice(wa, "f32")
+    solo.step(17)
+    solo.set_force("kolmogorov", params=(2e-4, 2))
+    solo.step(23)
+    ref = solo.get_populations().cpu().numpy()
+    solo.close()
+    la, lb = gpu_lattice(wa, "f32"), gpu_lattice(wb, "f32")
+    b = clbm.Batch([la, lb])
+    b.step(17)
+    la.set_force("kolmogorov", params=(2e-4, 2))
+    b.step(23)
+    assert np.array_equal(la.get_populations().cpu().numpy(), ref)
+    b.close()
+    la.close()
+    lb.close()
+
+
 def test_batch_step_and_autotune_keep_results(tmp_path):
     from paper_1705_11092_amd import clbm
     wls = [inputs.kolmogorov(n, 3e-6, 1, 0.9) for n in (32, 45, 100, 180)]
