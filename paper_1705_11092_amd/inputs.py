@@ -100,6 +100,42 @@ def kolmogorov(n: int, A: float, k: int, tau: float, steps: int = 1000) -> Workl
                     meta={"A": A, "k": k, "nu": (tau - 0.5) / 3.0})
 
 
+def steady_taylor_green(N: int, Re: float, u0: float = 0.05, scheme: str = "consistent",
+                        steps: int = 0) -> Workload:
+    """Steady forced Taylor-Green flow of Sec. IV B on an N x N periodic box:
+    u_a = u0 [sin(phi x) sin(phi y), cos(phi x) cos(phi y)], phi = 2 pi/N,
+    held by the force F = 2 nu phi^2 u_a, with nu = u0 N / Re; started from
+    u_a and the density of p_a.  Rates: sb = s2, s1 = s2 for the
+    Lycett-Brown & Luo scheme and 1 otherwise, the rest 1."""
+    nu = u0 * N / Re
+    s2 = s_from_nu(nu)
+    phi = 2.0 * math.pi / N
+    x = np.arange(N, dtype=np.float64)[None, :]
+    y = np.arange(N, dtype=np.float64)[:, None]
+    ux = np.ascontiguousarray(np.broadcast_to(u0 * np.sin(phi * x) * np.sin(phi * y), (N, N)))
+    uy = np.ascontiguousarray(np.broadcast_to(u0 * np.cos(phi * x) * np.cos(phi * y), (N, N)))
+    rho = np.ascontiguousarray(np.broadcast_to(
+        RHO0 + 3.0 * 0.25 * u0 * u0 * (np.cos(2 * phi * x) - np.cos(2 * phi * y)), (N, N)))
+    fx = 2.0 * nu * phi * phi * ux
+    fy = 2.0 * nu * phi * phi * uy
+    s1 = s2 if scheme == "guo_lbl" else 1.0
+    return Workload(f"steady_tg_{N}_Re{Re:g}_{scheme}", N, N, 0, (1.0, s1, s2, s2, 1.0, 1.0),
+                    "field", (fx, fy), rho, ux, uy, steps,
+                    meta={"Re": Re, "nu": nu, "u0": u0, "scheme": scheme})
+
+
+def channel(width: int, Fx: float, s2: float, s3: float, s1: Optional[float] = None,
+            scheme: str = "consistent", length: int = 1) -> Workload:
+    """Poiseuille channel of Sec. IV A: `width` nodes between half-way
+    bounce-back walls, periodic in x over `length` nodes, from rest, every
+    rate s2 except s3 (and s1 = 1 unless given)."""
+    rho, ux, uy = _rest(length, width)
+    s1v = 1.0 if s1 is None else s1
+    return Workload(f"channel_{width}_{scheme}", length, width, 1, (s2, s1v, s2, s2, s3, s2),
+                    "const", (Fx, 0.0), rho, ux, uy, 0,
+                    meta={"Fx": Fx, "nu": (1.0 / s2 - 0.5) / 3.0, "scheme": scheme})
+
+
 def random_state(nx: int, ny: int, seed: int, amp_rho: float = 0.02,
                  amp_u: float = 0.05, bc_y: int = 0, s=None,
                  force: str = "field", amp_f: float = 1e-3, steps: int = 10) -> Workload:
