@@ -16,6 +16,10 @@ p50/p99 latency.
 
 `--calibrate-copy` instead runs a plain device copy of known size (the
 reference for scaling the HBM byte counters of rocprofv3).
+`--traffic-summary FETCH_STEP WRITE_STEP FETCH_COPY WRITE_COPY` (CPU only)
+turns the counter_collection.csv files of the four rocprofv3 --pmc runs
+listed in the summary into profiles/traffic_step_f32_tg4096.json, stamped
+with the hash of the kernel sources they were taken on.
 """
 from __future__ import annotations
 
@@ -150,6 +154,59 @@ def calibrate_copy(nbytes: int, reps: int):
     print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def _counter_values(path: str, name_part: str, counter: str):
+    import csv
+    out = []
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if name_part in row["Kernel_Name"] and row["Counter_Name"] == counter:
+                out.append(float(row["Counter_Value"]))
+    if not out:
+        raise SystemExit(f"{path}: no {counter} rows for kernels named like {name_part!r}")
+    return out
+
+
+def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
+    """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+    what the same counters read for a plain copy of copy_bytes, and write
+    the summary bench.py reports as roofline.traffic."""
+    import statistics
+    csvs = [os.path.join(d, "run_counter_collection.csv") for d in dirs]
+    step = "k_step<1, 4, 0, 0>"
+    fetch = _counter_values(csvs[0], step, "FETCH_SIZE")
+    write = _counter_values(csvs[1], step, "WRITE_SIZE")
+    cf = statistics.median(_counter_values(csvs[2], "copyBuffer", "FETCH_SIZE"))
+    cw = statistics.median(_counter_values(csvs[3], "copyBuffer", "WRITE_SIZE"))
+    kib = copy_bytes / 1024.0
+    fs, ws = kib / cf, kib / cw
+    rd = statistics.median(fetch) * 1024.0 * fs
+    wr = statistics.median(write) * 1024.0 * ws
+    alg = BYTES_PER_LUP["f32"] * n * n
+    base = "rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 bench.py {a}"
+    step_args = "--steps 5 --warmup 0 --no-cpu-baseline --no-extra"
+    copy_args = f"--calibrate-copy {copy_bytes}"
+    out = {
+        "kernel": "clbm::k_step<1, 4, 0, 0> (FP32 deviations, 4 nodes per thread, constant "
+                  "force, consistent scheme)",
+        "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
+        "kernel_hash": kernel_hash(),
+        "commands": [base.format(c="FETCH_SIZE", d=dirs[0], a=step_args),
+                     base.format(c="WRITE_SIZE", d=dirs[1], a=step_args),
+                     base.format(c="FETCH_SIZE", d=dirs[2], a=copy_args),
+                     base.format(c="WRITE_SIZE", d=dirs[3], a=copy_args)],
+        "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+        "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_scale": round(fs, 6), "write_scale": round(ws, 6),
+        "hbm_read_bytes_per_launch": int(rd), "hbm_write_bytes_per_launch": int(wr),
+        "hbm_bytes_per_launch": int(rd + wr), "algorithmic_bytes_per_launch": alg,
+        "ratio_to_algorithmic": round((rd + wr) / alg, 4),
+    }
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: out[k] for k in ("hbm_bytes_per_launch", "ratio_to_algorithmic",
+                                           "fetch_scale", "write_scale", "kernel_hash")}))
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle on the host cores: the same 4096^2 workload, as many steps
     as fit in about budget_s seconds after one timed probe step."""
@@ -183,7 +240,13 @@ def main():
                     help="only the main lattice (16-bit, batch and served legs skipped)")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--traffic-summary", nargs=4, default=None,
+                    metavar=("FETCH_STEP", "WRITE_STEP", "FETCH_COPY", "WRITE_COPY"))
     args = ap.parse_args()
+
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary)
+        return
 
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy, 5)
