@@ -76,7 +76,9 @@ typedef enum {
     CLBM_FORCE_NONE = 0,       /* F = 0                                      */
     CLBM_FORCE_CONST = 1,      /* params = {Fx, Fy}                          */
     CLBM_FORCE_KOLMOGOROV = 2, /* params = {A, k}: Fx = A sin(2 pi k y/ny)   */
-    CLBM_FORCE_FIELD = 3       /* fx, fy: device FP64 [ny][nx], copied in    */
+    CLBM_FORCE_FIELD = 3,      /* fx, fy: device FP64 [ny][nx], copied in    */
+    CLBM_FORCE_SHAN_CHEN = 4   /* params = {G, psi0, rho_ref}: the Shan-Chen
+                                  interaction of the current density, Sec. IV C */
 } clbm_force_kind;
 
 /* Forcing scheme.  CONSISTENT is the paper's (Eq. 12).  GUO_LBL is the
@@ -126,12 +128,22 @@ int clbm_destroy(clbm_handle *h);
 /* Set the body force F(x) of Eqs. (12)-(15).  CONST and KOLMOGOROV read
  * params[2] (host); FIELD copies the caller's device arrays fx, fy (FP64
  * [ny][nx]) into a library-owned device buffer in the arithmetic type, so
- * the caller may free them once the stream has passed this call.  A new
- * force applies from the next step; clbm_init uses the force set before it.
- * Does not wait for the device (buffers are allocated and freed in stream
- * order).
+ * the caller may free them once the stream has passed this call.
+ * SHAN_CHEN reads params[3] = {G, psi0, rho_ref} (host) and makes the force
+ * depend on the state (Sec. IV C): at every step, before any node collides,
+ * a pass writes psi = psi0 exp(-rho_ref / rho) of each node's pre-collision
+ * density (Eq. 11) into a library-owned [ny][nx] plane in the arithmetic
+ * type; the step then takes F(x) = -G psi(x) sum_i w_i psi(x + e_i) e_i
+ * with w = 1/3 on the axes and 1/12 on the diagonals.  G < 0 attracts
+ * (the phase-separating sign).  Needs a periodic lattice (bc_y periodic);
+ * such a handle cannot join a batch.  clbm_init, clbm_moments and
+ * clbm_error_norms take F from the density of the state they read.
+ * A new force applies from the next step; clbm_init uses the force set
+ * before it.  Does not wait for the device (buffers are allocated and freed
+ * in stream order).
  * Errors: CLBM_EINVAL (unknown kind, missing params or arrays, non-finite
- * values), CLBM_EHIP. */
+ * values, SHAN_CHEN with psi0 or rho_ref not > 0 or bounce-back walls),
+ * CLBM_EHIP. */
 int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const double *fx,
                    const double *fy);
 

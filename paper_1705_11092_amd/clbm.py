@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libclbm.so")
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f16sr": 4, "bf16sr": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16sr": 2, "bf16sr": 2}
 BC = {"periodic": 0, "bounceback": 1}
-FORCE = {"none": 0, "const": 1, "kolmogorov": 2, "field": 3}
+FORCE = {"none": 0, "const": 1, "kolmogorov": 2, "field": 3, "shan_chen": 4}
 SCHEME = {"consistent": 0, "guo_lbl": 1}
 
 CLBM_OK, CLBM_EINVAL, CLBM_EHIP, CLBM_ESTATE, CLBM_ENONFINITE = 0, -1, -2, -3, -4
@@ -177,7 +177,7 @@ class Lattice:
     def set_force(self, kind: str, params=None, fx=None, fy=None):
         p = None
         if params is not None:
-            arr = (ctypes.c_double * 2)(*[float(v) for v in params])
+            arr = (ctypes.c_double * len(params))(*[float(v) for v in params])
             p = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
         with torch.cuda.stream(self.stream):
             tfx = _field(fx, (self.ny, self.nx), self.device)

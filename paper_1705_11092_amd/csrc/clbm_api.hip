@@ -313,12 +313,23 @@ int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const dou
         break;
     }
     case CLBM_FORCE_KOLMOGOROV:
-    case CLBM_FORCE_FIELD: {
-        const size_t bytes = kind == CLBM_FORCE_KOLMOGOROV ? rb * (size_t)d.ny : 2 * rb * (size_t)n;
+    case CLBM_FORCE_FIELD:
+    case CLBM_FORCE_SHAN_CHEN: {
+        const size_t bytes = kind == CLBM_FORCE_KOLMOGOROV ? rb * (size_t)d.ny
+                             : kind == CLBM_FORCE_FIELD    ? 2 * rb * (size_t)n
+                                                           : rb * (size_t)n;
         if (kind == CLBM_FORCE_KOLMOGOROV) {
             if (!params) return fail(CLBM_EINVAL, "KOLMOGOROV force needs params {A, k}");
             if (!std::isfinite(params[0]) || !std::isfinite(params[1]))
                 return fail(CLBM_EINVAL, "force parameters are not finite");
+        } else if (kind == CLBM_FORCE_SHAN_CHEN) {
+            if (!params) return fail(CLBM_EINVAL, "SHAN_CHEN force needs params {G, psi0, rho_ref}");
+            if (!std::isfinite(params[0]) || !std::isfinite(params[1]) || !std::isfinite(params[2]))
+                return fail(CLBM_EINVAL, "force parameters are not finite");
+            if (!(params[1] > 0.0) || !(params[2] > 0.0))
+                return fail(CLBM_EINVAL, "SHAN_CHEN needs psi0 > 0 and rho_ref > 0");
+            if (d.bc_y != CLBM_Y_PERIODIC)
+                return fail(CLBM_EINVAL, "SHAN_CHEN needs a periodic lattice");
         } else {
             int rc = check_device_range(fx, sizeof(double) * n, "fx");
             if (rc) return rc;
@@ -332,9 +343,15 @@ int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const dou
         if (kind == CLBM_FORCE_KOLMOGOROV) {
             d.force_mode = clbm::FM_ROW;
             HIPCHK(clbm::launch_force_table(d, h->force_buf, params[0], params[1], h->stream));
-        } else {
+        } else if (kind == CLBM_FORCE_FIELD) {
             d.force_mode = clbm::FM_FIELD;
             HIPCHK(clbm::launch_force_field(d, h->force_buf, fx, fy, h->stream));
+        } else {
+            // The psi plane is filled from the state before each use.
+            d.force_mode = clbm::FM_SC;
+            d.sc_g = params[0];
+            d.sc_psi0 = params[1];
+            d.sc_rho = params[2];
         }
         d.force = h->force_buf;
         d.Fx = d.Fy = 0.0;
@@ -356,6 +373,7 @@ int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double 
     if (rho && (rc = check_device_range(rho, fb, "rho"))) return rc;
     if (ux && (rc = check_device_range(ux, fb, "ux"))) return rc;
     if (uy && (rc = check_device_range(uy, fb, "uy"))) return rc;
+    if (h->d.force_mode == clbm::FM_SC) HIPCHK(clbm::launch_psi(h->d, -1, rho, h->stream));
     HIPCHK(clbm::launch_init(h->d, 0, rho, ux, uy, h->stream));
     h->parity = 0;
     h->steps = 0;
@@ -397,6 +415,7 @@ int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *to
     if (ux && (rc = check_device_range(ux, fb, "ux"))) return rc;
     if (uy && (rc = check_device_range(uy, fb, "uy"))) return rc;
     int nb = 0;
+    if (h->d.force_mode == clbm::FM_SC) HIPCHK(clbm::launch_psi(h->d, h->parity, nullptr, h->stream));
     HIPCHK(clbm::launch_moments(h->d, h->parity, rho, ux, uy, nullptr, nullptr, h->partials, &nb,
                                 h->stream));
     if (!totals) return CLBM_OK;
@@ -423,6 +442,7 @@ int clbm_error_norms(clbm_handle *h, const double *ux_ref, const double *uy_ref,
     if ((rc = check_device_range(ux_ref, fb, "ux_ref"))) return rc;
     if ((rc = check_device_range(uy_ref, fb, "uy_ref"))) return rc;
     int nb = 0;
+    if (h->d.force_mode == clbm::FM_SC) HIPCHK(clbm::launch_psi(h->d, h->parity, nullptr, h->stream));
     HIPCHK(clbm::launch_moments(h->d, h->parity, nullptr, nullptr, nullptr, ux_ref, uy_ref,
                                 h->partials, &nb, h->stream));
     double *w = pinned_words();
@@ -650,8 +670,11 @@ int batch_run(clbm_batch *b, const int64_t *nsteps)
         if (nsteps[j] > INT32_MAX) return fail(CLBM_EINVAL, "step count too large for one call");
         maxn = std::max(maxn, nsteps[j]);
     }
-    for (auto *h : b->lats)
+    for (auto *h : b->lats) {
         if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
+        if (h->d.force_mode == clbm::FM_SC)
+            return fail(CLBM_EINVAL, "a Shan-Chen lattice steps alone, not in a batch");
+    }
     if (maxn == 0) return CLBM_OK;
     batch_refresh(b);
     int rc = batch_upload(b, nsteps);
@@ -768,8 +791,11 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
 {
     g_err.clear();
     if (!b) return fail(CLBM_EINVAL, "batch is NULL");
-    for (auto *h : b->lats)
+    for (auto *h : b->lats) {
         if (!h->ready) return fail(CLBM_ESTATE, "a lattice of the batch has no state yet");
+        if (h->d.force_mode == clbm::FM_SC)
+            return fail(CLBM_EINVAL, "a Shan-Chen lattice steps alone, not in a batch");
+    }
     batch_refresh(b);
     const std::string sig = batch_signature(b);
     if (cache_path) {

@@ -10,7 +10,8 @@ namespace clbm {
 enum ForceMode {
     FM_CONST = 0,  // (Fx, Fy) of the descriptor at every node (zero = no force)
     FM_ROW = 1,    // Fx from a per-row table, Fy = 0 (Kolmogorov forcing)
-    FM_FIELD = 2   // fx, fy planes [ny][nx] in the arithmetic type
+    FM_FIELD = 2,  // fx, fy planes [ny][nx] in the arithmetic type
+    FM_SC = 3      // Shan-Chen: F from the psi plane [ny][nx] of this step
 };
 
 // Threads per block of every step kernel.
@@ -43,6 +44,7 @@ struct LatDesc {
     int64_t tile0;       // batch: first tile of this lattice in its group
     int64_t ntiles;      // batch: tiles of this lattice
     double Fx, Fy;       // FM_CONST force density
+    double sc_g, sc_psi0, sc_rho;  // FM_SC: G, psi0 and rho_ref of psi = psi0 exp(-rho_ref/rho)
     double rho0;
     double om1, omb, om2, om3, om4, h3, h2;  // 1 - s and force weights
 };
@@ -88,6 +90,10 @@ hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double 
 hipError_t launch_force_table(const LatDesc &d, void *table, double A, double k, hipStream_t s);
 hipError_t launch_force_field(const LatDesc &d, void *field, const double *fx, const double *fy,
                               hipStream_t s);
+// Shan-Chen: psi = psi0 exp(-rho_ref / rho) per node into d.force, from the
+// state in buffer src, or (rho != NULL) from a given density field, or
+// (src < 0, rho == NULL) from the rest density.
+hipError_t launch_psi(const LatDesc &d, int src, const double *rho, hipStream_t s);
 // Partial blocks the moments kernel uses for a lattice of n nodes.
 int moments_blocks(int64_t n);
 

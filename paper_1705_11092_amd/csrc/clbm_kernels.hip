@@ -105,11 +105,27 @@ __device__ __forceinline__ void force_at(const LatDesc &d, int x, int y, R &Fx, 
     } else if (FM == FM_ROW) {
         Fx = static_cast<const R *>(d.force)[y];
         Fy = R(0);
-    } else {
+    } else if (FM == FM_FIELD) {
         const R *f = static_cast<const R *>(d.force);
         const int64_t n = (int64_t)y * d.nx + x;
         Fx = f[n];
         Fy = f[(int64_t)d.nx * d.ny + n];
+    } else {
+        // Shan-Chen interaction (Sec. IV C): F = -G psi(x) sum_i w_i psi(x + e_i) e_i,
+        // w = 1/3 for the four axis neighbours and 1/12 for the diagonals;
+        // periodic in x and y.
+        const R *psi = static_cast<const R *>(d.force);
+        const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+        const int64_t rm = (int64_t)ym * d.nx, r0 = (int64_t)y * d.nx, rp = (int64_t)yp * d.nx;
+        const R third = R(1) / R(3), twelfth = R(1) / R(12);
+        const R sx = third * (psi[r0 + xp] - psi[r0 + xm]) +
+                     twelfth * ((psi[rp + xp] - psi[rp + xm]) + (psi[rm + xp] - psi[rm + xm]));
+        const R sy = third * (psi[rp + x] - psi[rm + x]) +
+                     twelfth * ((psi[rp + xp] + psi[rp + xm]) - (psi[rm + xp] + psi[rm + xm]));
+        const R g = -R(d.sc_g) * psi[r0 + x];
+        Fx = g * sx;
+        Fy = g * sy;
     }
 }
 
@@ -328,10 +344,37 @@ __device__ __forceinline__ void force_any(const LatDesc &d, int x, int y, double
         force_at<R, FM_CONST>(d, x, y, fx, fy);
     else if (d.force_mode == FM_ROW)
         force_at<R, FM_ROW>(d, x, y, fx, fy);
-    else
+    else if (d.force_mode == FM_FIELD)
         force_at<R, FM_FIELD>(d, x, y, fx, fy);
+    else
+        force_at<R, FM_SC>(d, x, y, fx, fy);
     Fx = (double)fx;
     Fy = (double)fy;
+}
+
+// psi(rho) = psi0 exp(-rho_ref / rho) (Sec. IV C) of the pre-collision
+// density of buffer src (the gather of the stored state, Eq. 11), of a given
+// density field, or of the rest density.
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_psi(LatDesc d, int src, const double *rho_in)
+{
+    using R = typename Storage<ST>::R;
+    R *psi = static_cast<R *>(const_cast<void *>(d.force));
+    const int64_t n = (int64_t)d.nx * d.ny;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(p / d.nx), x = (int)(p - (int64_t)y * d.nx);
+        R rho = R(d.rho0);  // src < 0 without a field: the rest density
+        if (rho_in) {
+            rho = R(rho_in[p]);
+        } else if (src >= 0) {
+            R dr = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dr += R(get_pre<ST>(d, src, i, x, y));
+            rho = R(d.rho0) + dr;
+        }
+        psi[p] = R(d.sc_psi0) * exp(-R(d.sc_rho) / rho);
+    }
 }
 
 template <int ST>
@@ -516,6 +559,12 @@ hipError_t step_dispatch(const LatDesc &d, int src, hipStream_t s)
     case FM_FIELD * 2 + SCH_GUO_LBL:
         k_step<ST, VEC, FM_FIELD, SCH_GUO_LBL><<<grid, block, 0, s>>>(e, src, ntiles);
         break;
+    case FM_SC * 2 + SCH_CONSISTENT:
+        k_step<ST, VEC, FM_SC, SCH_CONSISTENT><<<grid, block, 0, s>>>(e, src, ntiles);
+        break;
+    case FM_SC * 2 + SCH_GUO_LBL:
+        k_step<ST, VEC, FM_SC, SCH_GUO_LBL><<<grid, block, 0, s>>>(e, src, ntiles);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -558,6 +607,12 @@ hipError_t batch_dispatch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntile
 
 hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s)
 {
+    if (d.force_mode == FM_SC) {
+        // The interaction force needs every neighbour's psi of this step
+        // before any node collides: a pass of its own.
+        const hipError_t e = launch_psi(d, src, nullptr, s);
+        if (e != hipSuccess) return e;
+    }
     switch (d.storage) {
     case ST_F64:
         return vec == 1 ? step_dispatch<ST_F64, 1>(d, src, s) : step_dispatch<ST_F64, 2>(d, src, s);
@@ -637,6 +692,13 @@ hipError_t launch_init(const LatDesc &d, int dst, const double *rho, const doubl
 {
     const int g = helper_blocks((int64_t)d.nx * d.ny);
     CLBM_BY_STORAGE(k_init, g, d, dst, rho, ux, uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_psi(const LatDesc &d, int src, const double *rho, hipStream_t s)
+{
+    const int g = helper_blocks((int64_t)d.nx * d.ny);
+    CLBM_BY_STORAGE(k_psi, g, d, src, rho);
     return hipGetLastError();
 }
 

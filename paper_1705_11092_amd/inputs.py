@@ -38,7 +38,7 @@ class Workload:
     ny: int
     bc_y: int  # 0 periodic, 1 half-way bounce-back walls
     s: Tuple[float, float, float, float, float, float]  # s0, s1, sb, s2, s3, s4
-    force_kind: str  # "none" | "const" | "kolmogorov" | "field"
+    force_kind: str  # "none" | "const" | "kolmogorov" | "field" | "shan_chen"
     force_params: tuple
     rho: np.ndarray  # [ny, nx]
     ux: np.ndarray
@@ -134,6 +134,41 @@ def channel(width: int, Fx: float, s2: float, s3: float, s1: Optional[float] = N
     return Workload(f"channel_{width}_{scheme}", length, width, 1, (s2, s1v, s2, s2, s3, s2),
                     "const", (Fx, 0.0), rho, ux, uy, 0,
                     meta={"Fx": Fx, "nu": (1.0 / s2 - 0.5) / 3.0, "scheme": scheme})
+
+
+def droplet(n: int = 200, R: float = 50.0, s3: float = 1.0, s2: float = 1.4,
+            scheme: str = "consistent", G: float = -10.0 / 3.0, psi0: float = 1.0,
+            rho_ref: float = 1.0, rho_l: float = 2.783, rho_v: float = 0.3675,
+            steps: int = 0) -> Workload:
+    """Static droplet of Sec. IV C on an n x n periodic box: density rho_l
+    inside a circle of radius R about the box centre ((n - 1)/2, (n - 1)/2),
+    rho_v outside, at rest, under the Shan-Chen force with parameters
+    (G, psi0, rho_ref).  Rates: sb = s2 (= s_v), s3 as given, the rest 1;
+    s1 = s2 for the Lycett-Brown & Luo scheme (momentum conservation)."""
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2.0
+    rho = np.where((x - c) ** 2 + (y - c) ** 2 < R * R, rho_l, rho_v)
+    z = np.zeros((n, n))
+    s1 = s2 if scheme == "guo_lbl" else 1.0
+    return Workload(f"droplet_{n}_R{R:g}_s3_{s3:g}_{scheme}", n, n, 0, (1.0, s1, s2, s2, s3, 1.0),
+                    "shan_chen", (float(G), float(psi0), float(rho_ref)), rho, z, z.copy(), steps,
+                    meta={"R": R, "scheme": scheme, "rho_l": rho_l, "rho_v": rho_v})
+
+
+def slab(n: int = 128, width: int = 64, ny: int = 4, s2: float = 1.4, s3: float = 1.0,
+         G: float = -10.0 / 3.0, rho_l: float = 2.783, rho_v: float = 0.3675,
+         steps: int = 0) -> Workload:
+    """Flat liquid slab (a planar interface pair): rho_l on the `width` middle
+    columns of an n x ny periodic box, rho_v elsewhere, at rest, under the
+    Shan-Chen force.  With no curvature both phases settle at the
+    coexistence densities."""
+    x = np.arange(n, dtype=np.float64)[None, :]
+    lo = (n - width) // 2
+    rho = np.ascontiguousarray(np.broadcast_to(np.where((x >= lo) & (x < lo + width), rho_l, rho_v),
+                                               (ny, n)))
+    z = np.zeros((ny, n))
+    return Workload(f"slab_{n}x{ny}_w{width}", n, ny, 0, (1.0, 1.0, s2, s2, s3, 1.0), "shan_chen",
+                    (float(G), 1.0, 1.0), rho, z, z.copy(), steps, meta={"width": width})
 
 
 def random_state(nx: int, ny: int, seed: int, amp_rho: float = 0.02,

@@ -19,6 +19,13 @@ def oracle_force(wl):
 
 
 def oracle_run(wl, steps, scheme=oracle.SCHEME_CONSISTENT, nthreads=0):
+    if wl.force_kind == "shan_chen":
+        from oracle import shan_chen
+        G, psi0, rho_ref = wl.force_params
+        f = shan_chen.start(wl.rho, wl.ux, wl.uy, G, psi0, rho_ref)
+        f = shan_chen.run(f, wl.s, steps, G, psi0, rho_ref, scheme=scheme, nthreads=nthreads)
+        rho, ux, uy = shan_chen.state(f, G, psi0, rho_ref)
+        return f, rho, ux, uy
     fx, fy = oracle_force(wl)
     f = oracle.init(wl.rho, wl.ux, wl.uy, fx, fy)
     if steps:
