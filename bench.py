@@ -9,8 +9,8 @@ lattice (Eqs. 9-15).  Inputs are resident in HBM before timing starts.
 Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
 algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
 oracle's throughput on the host cores for a bounded sample of the same
-workload.  Beside it, in the same line: the same lattice with 16-bit
-storage, the batch of 256 uneven Kolmogorov lattices advanced by one
+workload.  Beside it, in the same line: the same lattice streamed in place
+(one buffer), the same lattice with 16-bit storage, the batch of 256 uneven Kolmogorov lattices advanced by one
 persistent launch per step, and a served Poisson stream of solves with its
 p50/p99 latency.
 
@@ -36,7 +36,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_LUP = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36, "f16sr": 36, "bf16sr": 36}
-KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_kernels.hip",
+KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_step_f32.hip",
+                  "paper_1705_11092_amd/csrc/clbm_step.h",
+                  "paper_1705_11092_amd/csrc/clbm_layout.h",
+                  "paper_1705_11092_amd/csrc/clbm_force.h",
                   "paper_1705_11092_amd/csrc/clbm_device.h",
                   "paper_1705_11092_amd/csrc/clbm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_tg4096.json")
@@ -65,12 +68,12 @@ def measured_traffic(storage: str, n_nodes: int):
     return t.get("hbm_bytes_per_launch")
 
 
-def run_gpu(n: int, storage: str, steps: int, warmup: int):
+def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False):
     import torch
     from paper_1705_11092_amd import clbm, inputs
 
     wl = inputs.taylor_green(n, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=steps)
-    lat = clbm.lattice_from_workload(wl, storage=storage)
+    lat = clbm.lattice_from_workload(wl, storage=storage, inplace=inplace)
     stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -290,6 +293,12 @@ def main():
     }
     if not args.no_extra:
         extra = {}
+        msi, _, _ = run_gpu(args.n, args.storage, args.steps, args.warmup, inplace=True)
+        m = nodes / (msi / args.steps / 1e3) / 1e6
+        extra[f"{args.storage}_in_place"] = {
+            "mlups": round(m, 1), "ms_per_step": round(msi / args.steps, 5),
+            "hbm_frac": round(m * 1e6 * bpl / 8e12, 4),
+            "footprint_bytes": nodes * bpl // 2}
         for st in ("f16", "bf16", "f16sr", "bf16sr"):
             ms16, _, _ = run_gpu(args.n, st, args.steps, args.warmup)
             m = nodes / (ms16 / args.steps / 1e3) / 1e6

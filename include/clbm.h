@@ -81,6 +81,15 @@ typedef enum {
                                   interaction of the current density, Sec. IV C */
 } clbm_force_kind;
 
+/* How streaming (Eq. 10) is stored.  TWO_BUFFERS: each step reads one
+ * buffer and writes the other (pull form).  IN_PLACE: one buffer, the AA
+ * pattern -- steps alternate between reading a node's own slots and writing
+ * them back reversed, and reading the neighbours' reversed slots and writing
+ * to the neighbours; every location is read and written by one node only,
+ * so no step races.  Half the memory, the same bytes moved per step and
+ * bitwise the same results. */
+typedef enum { CLBM_STREAM_TWO_BUFFERS = 0, CLBM_STREAM_IN_PLACE = 1 } clbm_streaming;
+
 /* Forcing scheme.  CONSISTENT is the paper's (Eq. 12).  GUO_LBL is the
  * Lycett-Brown & Luo scheme with Guo's term (Eq. 21), kept for the paper's
  * comparisons; it needs s1 = s2 to conserve momentum (Remark 5). */
@@ -95,13 +104,14 @@ typedef struct {
     int32_t bc_y;     /* clbm_bc_y                                             */
     int32_t storage;  /* clbm_storage                                          */
     int32_t scheme;   /* clbm_scheme                                           */
-    int32_t reserved; /* must be 0                                             */
+    int32_t streaming; /* clbm_streaming                                      */
     /* S = diag(s0, s1, s1, sb, s2, s2, s3, s3, s4) (Sec. II A); each rate in
      * (0, 2).  s2 = 1/(3 nu + 0.5), sb = 1/(3 xi + 0.5). */
     double s0, s1, sb, s2, s3, s4;
     double rho0;      /* reference density of the deviation storage, > 0     */
     void *pop_a;      /* device buffer of clbm_buffer_bytes(nx, ny, storage) */
-    void *pop_b;      /* second buffer of the same size (ping-pong)          */
+    void *pop_b;      /* TWO_BUFFERS: second buffer of the same size;
+                         IN_PLACE: must be NULL                              */
     void *stream;     /* hipStream_t for all work of this handle; NULL = the
                          null stream                                         */
 } clbm_config;
@@ -115,8 +125,8 @@ size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage);
 /* Validate cfg and create a handle.  Allocates the FP64 reduction scratch
  * (at most 24 KB of device memory, stream-ordered on cfg->stream).
  * Errors: CLBM_EINVAL (any field out of range, null buffers, pop_a ==
- * pop_b, buffers that are not device memory or smaller than
- * clbm_buffer_bytes), CLBM_EHIP. */
+ * pop_b with two buffers, a pop_b with IN_PLACE, buffers that are not
+ * device memory or smaller than clbm_buffer_bytes), CLBM_EHIP. */
 int clbm_create(const clbm_config *cfg, clbm_handle **out);
 
 /* Release the handle without waiting for the device: the device memory it
@@ -157,8 +167,9 @@ int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double 
 
 /* Advance nsteps >= 0 time steps: per node the collision of Eq. (12) and
  * the back-transform of Eq. (9), then streaming (Eq. 10), fused in one
- * kernel launch per step (pull form: each node gathers its pre-collision
- * populations from its neighbours' post-collision ones).  Long runs replay
+ * kernel launch per step (two buffers: each node gathers its pre-collision
+ * populations from its neighbours' post-collision ones; in place: the AA
+ * pattern of clbm_streaming).  Long runs replay
  * a captured hipGraph.  Errors: CLBM_ESTATE before clbm_init or
  * clbm_set_populations, CLBM_EINVAL (nsteps < 0), CLBM_EHIP. */
 int clbm_step(clbm_handle *h, int64_t nsteps);
@@ -193,6 +204,15 @@ int clbm_set_populations(clbm_handle *h, const double *f);
  * directly.  Default 64. */
 int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
 
+/* Cap on the step kernel's resident blocks per compute unit (0 = none, or
+ * 2..16), enforced with unused LDS per block.  Results do not depend on it.
+ * The default comes from measurements on MI355X: lattices whose step
+ * traffic exceeds the 256 MB Infinity Cache stream HBM fastest with 3
+ * blocks per CU for FP32 and 2 for FP64 (4 for cache-resident FP64); the
+ * 16-bit kernels run uncapped.  Errors: CLBM_EINVAL. */
+int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu);
+int32_t clbm_get_occupancy(const clbm_handle *h); /* -1 for NULL */
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *clbm_last_error(void);
 
@@ -206,7 +226,8 @@ double clbm_s_from_nu(double nu);
 /* ---- batches of lattices ----------------------------------------------- */
 
 /* A batch advances many independent lattices (any sizes, storages, forces,
- * rates and y boundaries) with one persistent kernel launch per time step.
+ * rates, y boundaries and streaming forms; not Shan-Chen) with one
+ * persistent kernel launch per time step and kernel kind.
  * Each node is updated by exactly the arithmetic of clbm_step, so a
  * lattice's result is bitwise the same alone and in any batch. */
 typedef struct clbm_batch clbm_batch;
@@ -230,7 +251,12 @@ int clbm_batch_step_each(clbm_batch *b, const int64_t *nsteps);
 /* Time the kernel variants of the batch on its own lattices and keep the
  * fastest (results do not depend on the variant).  With cache_path set,
  * look the choice up first and record it after, keyed by architecture and
- * batch shape.  *chosen (optional) receives the variant index. */
+ * batch shape.  *chosen (optional) receives the variant index.  The timed
+ * launches leave every lattice's state untouched: with two buffers they
+ * write the spare one, in-place lattices write a scratch allocation the
+ * size of the largest of them (stream-ordered, freed on return).
+ * Errors: CLBM_ESTATE (a lattice without state), CLBM_EINVAL (Shan-Chen),
+ * CLBM_EHIP. */
 int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen);
 
 /* Number of kernel variants, and the one in use (settable). */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libclbm.so")
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f16sr": 4, "bf16sr": 5}
 ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16sr": 2, "bf16sr": 2}
 BC = {"periodic": 0, "bounceback": 1}
+STREAM_TWO_BUFFERS, STREAM_IN_PLACE = 0, 1
 FORCE = {"none": 0, "const": 1, "kolmogorov": 2, "field": 3, "shan_chen": 4}
 SCHEME = {"consistent": 0, "guo_lbl": 1}
 
@@ -35,7 +36,7 @@ class _Config(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("bc_y", ctypes.c_int32), ("storage", ctypes.c_int32),
-        ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("streaming", ctypes.c_int32),
         ("s0", ctypes.c_double), ("s1", ctypes.c_double), ("sb", ctypes.c_double),
         ("s2", ctypes.c_double), ("s3", ctypes.c_double), ("s4", ctypes.c_double),
         ("rho0", ctypes.c_double),
@@ -58,6 +59,8 @@ def _load():
         "clbm_set_force": (ctypes.c_int, [vp, i32, dp, vp, vp]),
         "clbm_init": (ctypes.c_int, [vp, vp, vp, vp]),
         "clbm_step": (ctypes.c_int, [vp, i64]),
+        "clbm_set_occupancy": (ctypes.c_int, [vp, i32]),
+        "clbm_get_occupancy": (i32, [vp]),
         "clbm_step_count": (i64, [vp]),
         "clbm_moments": (ctypes.c_int, [vp, vp, vp, vp, dp]),
         "clbm_error_norms": (ctypes.c_int, [vp, vp, vp, dp]),
@@ -90,6 +93,7 @@ EXPORTED = (
     "clbm_buffer_bytes", "clbm_create", "clbm_destroy", "clbm_set_force", "clbm_init",
     "clbm_step", "clbm_step_count", "clbm_moments", "clbm_error_norms",
     "clbm_get_populations", "clbm_set_populations", "clbm_set_graph_steps",
+    "clbm_set_occupancy", "clbm_get_occupancy",
     "clbm_last_error", "clbm_nonslip_s3", "clbm_s_from_nu", "clbm_batch_create",
     "clbm_batch_step", "clbm_batch_step_each", "clbm_batch_autotune",
     "clbm_batch_variant_count", "clbm_batch_set_variant", "clbm_batch_get_variant",
@@ -134,8 +138,10 @@ class Lattice:
 
     def __init__(self, nx: int, ny: int, s: Sequence[float], storage: str = "f32",
                  bc_y: str = "periodic", rho0: float = 1.0, scheme: str = "consistent",
-                 device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+                 device: str = "cuda", stream: Optional[torch.cuda.Stream] = None,
+                 inplace: bool = False):
         self.nx, self.ny, self.storage = int(nx), int(ny), storage
+        self.inplace = bool(inplace)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = buffer_bytes(self.nx, self.ny, storage)
@@ -143,11 +149,14 @@ class Lattice:
             raise ClbmError(CLBM_EINVAL, "invalid lattice size or storage")
         with torch.cuda.stream(self.stream):
             self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.pop_b = (None if self.inplace else
+                          torch.empty(nbytes, dtype=torch.uint8, device=self.device))
         s = [float(v) for v in s]
-        cfg = _Config(self.nx, self.ny, BC[bc_y], STORAGE[storage], SCHEME[scheme], 0,
+        cfg = _Config(self.nx, self.ny, BC[bc_y], STORAGE[storage], SCHEME[scheme],
+                      STREAM_IN_PLACE if self.inplace else STREAM_TWO_BUFFERS,
                       s[0], s[1], s[2], s[3], s[4], s[5], float(rho0),
-                      self.pop_a.data_ptr(), self.pop_b.data_ptr(), self.stream.cuda_stream)
+                      self.pop_a.data_ptr(), None if self.inplace else self.pop_b.data_ptr(),
+                      self.stream.cuda_stream)
         self._cfg = cfg
         h = ctypes.c_void_p()
         _check(lib.clbm_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -172,7 +181,7 @@ class Lattice:
 
     @property
     def footprint_bytes(self) -> int:
-        return 2 * self.pop_a.numel()
+        return (1 if self.inplace else 2) * self.pop_a.numel()
 
     def set_force(self, kind: str, params=None, fx=None, fy=None):
         p = None
@@ -205,6 +214,15 @@ class Lattice:
 
     def set_graph_steps(self, n: int):
         _check(lib.clbm_set_graph_steps(self._h, int(n)))
+
+    @property
+    def occupancy(self) -> int:
+        """Cap on the step kernel's blocks per compute unit (0 = none)."""
+        return int(lib.clbm_get_occupancy(self._h))
+
+    @occupancy.setter
+    def occupancy(self, blocks_per_cu: int):
+        _check(lib.clbm_set_occupancy(self._h, int(blocks_per_cu)))
 
     def moments(self, fields: bool = True, totals: bool = True):
         """(rho, ux, uy, totals): FP64 device fields (or None) and the host
@@ -296,11 +314,12 @@ class Batch:
 
 
 def lattice_from_workload(wl, storage: str = "f32", device: str = "cuda",
-                          stream: Optional[torch.cuda.Stream] = None, init: bool = True) -> Lattice:
+                          stream: Optional[torch.cuda.Stream] = None, init: bool = True,
+                          inplace: bool = False, scheme: str = "consistent") -> Lattice:
     """A Lattice set up from an inputs.Workload (force then start state)."""
     lat = Lattice(wl.nx, wl.ny, wl.s, storage=storage,
                   bc_y="bounceback" if wl.bc_y == 1 else "periodic", rho0=wl.rho0,
-                  device=device, stream=stream)
+                  device=device, stream=stream, inplace=inplace, scheme=scheme)
     if wl.force_kind == "field":
         lat.set_force("field", fx=wl.force_params[0], fy=wl.force_params[1])
     elif wl.force_kind == "none":

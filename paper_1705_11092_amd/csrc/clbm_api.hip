@@ -62,6 +62,43 @@ bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
 
 // Default nodes per thread of the single-lattice step: 16-byte vectors for
 // FP64 and FP32, 8-byte vectors for 16-bit storage (fewer live registers).
+// Blocks per compute unit for the single-lattice step, measured on MI355X
+// (4096^2 and 1024^2 sweeps of 2..8 blocks per CU against no cap).  When a
+// step's traffic exceeds the 256 MB Infinity Cache, fewer resident waves
+// stream HBM faster for the wide types: FP32 is fastest at 3 blocks per CU
+// (196 us against 208 us uncapped at 4096^2), FP64 at 2 (376 against 397);
+// the 16-bit kernels, co-limited by ALU issue, want every wave they can get.
+// Cache-resident lattices: FP64 gains a little at 4, the rest at no cap.
+int default_occupancy(int storage, size_t bytes_per_step)
+{
+    const bool hbm = bytes_per_step > ((size_t)256 << 20);
+    switch (storage) {
+    case CLBM_F64: return hbm ? 2 : 4;
+    case CLBM_F32: return hbm ? 3 : 0;
+    default: return 0;
+    }
+}
+
+// Dynamic LDS per block that leaves room for exactly `occ` blocks on a
+// compute unit with lds_per_cu bytes (a block asks for lds_per_cu/(occ + 1/2),
+// rounded down to 256 bytes).
+size_t lds_for_occupancy(int occ)
+{
+    if (occ <= 0) return 0;
+    int dev = 0, per_cu = 0, per_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    size_t lds = (size_t)(per_cu / (occ + 0.5)) / 256 * 256;
+    if (lds > (size_t)per_block) return 0;  // cannot enforce: leave uncapped
+    return lds;
+}
+
 int default_vec(int storage)
 {
     switch (storage) {
@@ -160,6 +197,8 @@ struct clbm_handle {
     double *partials = nullptr;  // per-block FP64 partial sums (stream-ordered)
     double *d_out = nullptr;     // reduced totals on the device
     int vec = 4;
+    int occ = 0;                 // blocks per compute unit of the step kernel (0: no cap)
+    size_t lds = 0;              // dynamic LDS per block that enforces occ
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -181,7 +220,7 @@ int build_graph(clbm_handle *h, int parity)
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
-        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, h->cap);
+        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, h->lds, h->cap);
     hipError_t ce = hipStreamEndCapture(h->cap, &g);
     if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -226,17 +265,19 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     if (elem_bytes(cfg->storage) == 0) return fail(CLBM_EINVAL, "unknown storage");
     if (cfg->scheme != CLBM_SCHEME_CONSISTENT && cfg->scheme != CLBM_SCHEME_GUO_LBL)
         return fail(CLBM_EINVAL, "unknown scheme");
-    if (cfg->reserved != 0) return fail(CLBM_EINVAL, "reserved must be 0");
+    if (cfg->streaming != CLBM_STREAM_TWO_BUFFERS && cfg->streaming != CLBM_STREAM_IN_PLACE)
+        return fail(CLBM_EINVAL, "streaming must be CLBM_STREAM_TWO_BUFFERS or CLBM_STREAM_IN_PLACE");
+    const bool inplace = cfg->streaming == CLBM_STREAM_IN_PLACE;
     const double rates[6] = {cfg->s0, cfg->s1, cfg->sb, cfg->s2, cfg->s3, cfg->s4};
     for (double s : rates)
         if (!rate_ok(s)) return fail(CLBM_EINVAL, "every relaxation rate must lie in (0, 2]");
     if (!std::isfinite(cfg->rho0) || cfg->rho0 <= 0.0) return fail(CLBM_EINVAL, "rho0 must be > 0");
-    if (cfg->pop_a == cfg->pop_b) return fail(CLBM_EINVAL, "pop_a and pop_b must differ");
+    if (inplace && cfg->pop_b) return fail(CLBM_EINVAL, "in-place streaming takes no pop_b");
+    if (!inplace && cfg->pop_a == cfg->pop_b) return fail(CLBM_EINVAL, "pop_a and pop_b must differ");
     const size_t need = clbm_buffer_bytes(cfg->nx, cfg->ny, cfg->storage);
     int rc = check_device_range(cfg->pop_a, need, "pop_a");
     if (rc) return rc;
-    rc = check_device_range(cfg->pop_b, need, "pop_b");
-    if (rc) return rc;
+    if (!inplace && (rc = check_device_range(cfg->pop_b, need, "pop_b"))) return rc;
 
     clbm_handle *h = new clbm_handle();
     h->cfg = *cfg;
@@ -244,7 +285,8 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     LatDesc &d = h->d;
     std::memset(&d, 0, sizeof d);
     d.buf[0] = cfg->pop_a;
-    d.buf[1] = cfg->pop_b;
+    d.buf[1] = inplace ? cfg->pop_a : cfg->pop_b;
+    d.inplace = inplace ? 1 : 0;
     d.dstride = pitch_of(cfg->nx);
     d.rstride = 9 * pitch_of(cfg->nx);
     d.nx = cfg->nx;
@@ -262,6 +304,8 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.h3 = 1.0 - 0.5 * cfg->s3;
     d.h2 = 1.0 - 0.5 * cfg->s2;
     h->vec = default_vec(cfg->storage);
+    h->occ = default_occupancy(cfg->storage, 2 * need);
+    h->lds = lds_for_occupancy(h->occ);
 
     reap_retired();
     const int nb = clbm::moments_blocks((int64_t)cfg->nx * cfg->ny);
@@ -394,7 +438,7 @@ int clbm_step(clbm_handle *h, int64_t nsteps)
             HIPCHK(hipGraphLaunch(h->graph[h->parity], h->stream));
             left -= h->graph_steps;  // even, so the parity is unchanged
         } else {
-            HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, h->stream));
+            HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, h->lds, h->stream));
             h->parity ^= 1;
             left -= 1;
         }
@@ -488,6 +532,20 @@ int clbm_set_graph_steps(clbm_handle *h, int32_t steps)
     return CLBM_OK;
 }
 
+int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (blocks_per_cu != 0 && (blocks_per_cu < 2 || blocks_per_cu > 16))
+        return fail(CLBM_EINVAL, "blocks per compute unit must be 0 (no cap) or in [2, 16]");
+    drop_graphs(h);
+    h->occ = blocks_per_cu;
+    h->lds = lds_for_occupancy(blocks_per_cu);
+    return CLBM_OK;
+}
+
+int32_t clbm_get_occupancy(const clbm_handle *h) { return h ? h->occ : -1; }
+
 const char *clbm_last_error(void) { return g_err.c_str(); }
 
 double clbm_nonslip_s3(double s2) { return (16.0 - 8.0 * s2) / (8.0 - s2); }
@@ -531,7 +589,7 @@ struct clbm_batch {
     hipStream_t cap = nullptr;        // capture-only stream, created on first graph
     LatDesc *d_lats = nullptr;        // device lattice table (stream-ordered)
     struct Group {
-        int storage, mode, vec, l_lo, l_hi;  // mode = force_mode * 2 + scheme
+        int storage, key, vec, l_lo, l_hi;  // key = clbm::kernel_key
         int64_t ntiles;
     };
     std::vector<Group> groups;
@@ -544,16 +602,17 @@ struct clbm_batch {
 
 namespace {
 
-// Launch group of a lattice: storage type and (force mode, scheme).
-int group_key(const LatDesc &d) { return d.storage * 8 + d.force_mode * 2 + d.scheme; }
+// Launch group of a lattice: storage type and kernel (storage scheme, force
+// mode, forcing scheme).
+int group_key(const LatDesc &d) { return d.storage * clbm::kKernelKeys + clbm::kernel_key(d); }
 
-// Table order: grouped by storage, force mode and scheme (one launch per
-// group), caller order inside a group.
+// Table order: grouped by storage and kernel (one launch per group), caller
+// order inside a group.
 void batch_order(clbm_batch *b)
 {
     b->order.clear();
     b->keys.clear();
-    for (int key = 0; key < kStorageKinds * 8; ++key)
+    for (int key = 0; key < kStorageKinds * clbm::kKernelKeys; ++key)
         for (size_t j = 0; j < b->lats.size(); ++j)
             if (group_key(b->lats[j]->d) == key) b->order.push_back((int)j);
     for (auto *h : b->lats) b->keys.push_back(group_key(h->d));
@@ -582,7 +641,7 @@ void batch_geometry(clbm_batch *b)
             b->tab[pos] = d;
             ++pos;
         }
-        b->groups.push_back({st, d0.force_mode * 2 + d0.scheme, vec, lo, (int)pos, tiles});
+        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles});
     }
     retire_graph(b->graph, b->stream);
     b->graph = nullptr;
@@ -590,7 +649,9 @@ void batch_geometry(clbm_batch *b)
 
 // Refresh the table from the lattices (force, parity) with the steps each
 // takes in this call, and send it to the device through kernel arguments.
-int batch_upload(clbm_batch *b, const int64_t *nsteps)
+// With `scratch`, in-place lattices write there instead of into their state
+// (the autotuner's timed launches).
+int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
 {
     clbm::UploadPayload p;
     const int count = (int)b->order.size();
@@ -609,6 +670,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps)
             d.ntiles = g.ntiles;
             d.parity = h->parity;
             d.steps = (int32_t)nsteps[b->order[pos]];
+            if (scratch && d.inplace) d.buf[1] = scratch;
             p.d[k] = d;
         }
         HIPCHK(clbm::launch_upload(b->d_lats, first, n, p, b->stream));
@@ -634,7 +696,7 @@ int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
     const int64_t grid = (int64_t)b->cus * kVariants[b->variant].blocks_per_cu;
     for (const auto &g : b->groups) {
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
-        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.mode, g.vec, gg,
+        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.key, g.vec, gg,
                                   substep, s));
     }
     return CLBM_OK;
@@ -813,8 +875,17 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     // Time one step of every lattice per variant.  The timed launches read
     // the current state and write the other buffer without advancing the
     // lattices, so the state is untouched (the next real step overwrites
-    // that buffer).
+    // that buffer).  In-place lattices have no other buffer: their timed
+    // launches write one scratch allocation as large as the largest of
+    // them (all into the same place; its contents are never read).
     std::vector<int64_t> ones(b->lats.size(), 1);
+    size_t scratch_bytes = 0;
+    for (auto *h : b->lats)
+        if (h->d.inplace)
+            scratch_bytes = std::max(scratch_bytes,
+                                     clbm_buffer_bytes(h->d.nx, h->d.ny, h->d.storage));
+    void *scratch = nullptr;
+    if (scratch_bytes) HIPCHK(hipMallocAsync(&scratch, scratch_bytes, b->stream));
     hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
@@ -823,7 +894,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     int rc = CLBM_OK;
     for (int v = 0; v < kNumVariants && rc == CLBM_OK; ++v) {
         if ((rc = clbm_batch_set_variant(b, v))) break;
-        if ((rc = batch_upload(b, ones.data()))) break;
+        if ((rc = batch_upload(b, ones.data(), scratch))) break;
         const int reps = 5;
         for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_substep(b, 0, b->stream);
         if (rc) break;
@@ -846,6 +917,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
+    if (scratch) (void)hipFreeAsync(scratch, b->stream);
     if (rc) return rc;
     if ((rc = clbm_batch_set_variant(b, best))) return rc;
     if (chosen) *chosen = best;

@@ -25,7 +25,8 @@ constexpr int kRowAlign = 8;
 // Everything a kernel needs to step one lattice.  Passed by value to the
 // single-lattice kernel and stored in a device array for batches.
 struct LatDesc {
-    void *buf[2];        // ping-pong population buffers
+    void *buf[2];        // two buffers: ping-pong; in place: read buf[0], write buf[1]
+                         // (the same buffer outside the batch autotuner)
     const void *force;   // FM_ROW: table[ny]; FM_FIELD: fx plane then fy plane
     int64_t dstride;     // elements between the rows of two directions
     int64_t rstride;     // elements between two lattice rows (all 9 directions)
@@ -40,7 +41,7 @@ struct LatDesc {
     int32_t rows;        // rows per tile
     int32_t segs;        // tiles across one row
     int32_t vec;         // nodes per thread along x
-    int32_t pad_;
+    int32_t inplace;     // 0: two buffers (pull form); 1: one buffer, AA pattern
     int64_t tile0;       // batch: first tile of this lattice in its group
     int64_t ntiles;      // batch: tiles of this lattice
     double Fx, Fy;       // FM_CONST force density
@@ -68,13 +69,27 @@ inline void tile_geometry(int nx, int ny, int vec, int32_t *tpr, int32_t *rows, 
     *ntiles = (int64_t)(*segs) * ((ny + *rows - 1) / *rows);
 }
 
+// Step kernel of a lattice within its storage type: storage scheme, force
+// mode and forcing scheme.
+inline int kernel_key(const LatDesc &d) { return (d.inplace * 4 + d.force_mode) * 2 + d.scheme; }
+constexpr int kKernelKeys = 16;
+
 // Launchers (clbm_kernels.hip).  All return the hipError_t of the launch.
-hipError_t launch_step(const LatDesc &d, int src, int vec, hipStream_t s);
+// One step of a lattice: src is the buffer (two buffers) or phase (in
+// place) holding the state; lds bytes of unused LDS per block cap the
+// blocks resident on a compute unit (0: no cap).
+hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream_t s);
 // One time step of lattices [l_lo, l_hi) of a batch table (all of one
-// storage type and one mode = force_mode * 2 + scheme, tiles numbered
-// consecutively through their tile0 fields).
+// storage type and one kernel key, tiles numbered consecutively through
+// their tile0 fields).
 hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
-                        int mode, int vec, int grid, int substep, hipStream_t s);
+                        int key, int vec, int grid, int substep, hipStream_t s);
+// The same per storage type, one translation unit each (clbm_step_*.hip).
+template <int ST>
+hipError_t launch_step_st(const LatDesc &d, int src, int vec, size_t lds, hipStream_t s);
+template <int ST>
+hipError_t launch_batch_st(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int key,
+                           int vec, int grid, int substep, hipStream_t s);
 // Write n <= kUploadMax descriptors to lats[first..first+n) on the stream.
 hipError_t launch_upload(LatDesc *lats, int first, int n, const UploadPayload &p, hipStream_t s);
 hipError_t launch_batch_advance(LatDesc *lats, int count, int chunk, hipStream_t s);

@@ -1,0 +1,293 @@
+// clbm_step.h -- the fused collide-and-stream step (Eqs. 9-15 and the
+// streaming of Eq. 10) on VEC consecutive nodes of one row, the kernels
+// that run it over one lattice or a batch, and their dispatch over force
+// mode, scheme and storage scheme.  Included by one translation unit per
+// storage type (clbm_step_<type>.hip), which instantiates the launchers.
+//
+// Each thread gathers the pre-collision populations of its nodes, collides
+// them in registers and stores the post-collision values; every stored
+// value is read exactly once per step, so there is no reuse for LDS to
+// capture: the step is bound by HBM traffic, 2 x 9 values per node.  Loads
+// and stores are non-temporal.
+#pragma once
+
+#include "clbm_device.h"
+#include "clbm_internal.h"
+#include "clbm_force.h"
+#include "clbm_layout.h"
+
+namespace clbm {
+namespace {
+
+template <typename R>
+__device__ __forceinline__ Rates<R> rates_of(const LatDesc &d)
+{
+    Rates<R> rt;
+    rt.om1 = R(d.om1);
+    rt.omb = R(d.omb);
+    rt.om2 = R(d.om2);
+    rt.om3 = R(d.om3);
+    rt.om4 = R(d.om4);
+    rt.h3 = R(d.h3);
+    rt.h2 = R(d.h2);
+    rt.rho0 = R(d.rho0);
+    return rt;
+}
+
+// ---- the fused step on VEC consecutive nodes of one row -------------------
+
+// AA = false: two buffers, read buffer src, write buffer src ^ 1.
+// AA = true: in place, src is the phase; read buf[0], write buf[1] (the same
+// buffer, except for the batch autotuner's timed launches, which send the
+// writes to scratch memory).
+template <int ST, int VEC, int FM, int SCH, bool AA>
+__device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int x0)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    using R = typename S::R;
+    const T *in = static_cast<const T *>(d.buf[AA ? 0 : src]);
+    T *out = static_cast<T *>(d.buf[AA ? 1 : (src ^ 1)]);
+
+    const T *rowp[9];
+    int dxs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Loc s = AA ? aa_source(d, i, y, src) : source_of(d, i, y);
+        rowp[i] = in + (int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride;
+        dxs[i] = s.dx;
+    }
+
+    const bool interior = x0 >= 1 && x0 + VEC < d.nx;
+    R g[VEC][9];
+    if (interior) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const Pack<T, VEC> p = load_pack<T, VEC>(rowp[i] + x0 - dxs[i]);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) g[k][i] = S::to_r(p.v[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const int x = x0 + k < d.nx ? x0 + k : d.nx - 1;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[k][i] = S::to_r(rowp[i][wrap_x(x - dxs[i], d.nx)]);
+        }
+    }
+
+    const Rates<R> rt = rates_of<R>(d);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        R Fx, Fy;
+        force_at<R, FM>(d, x0 + k < d.nx ? x0 + k : d.nx - 1, y, Fx, Fy);
+        collide<R, SCH>(g[k], Fx, Fy, rt);
+    }
+
+    if constexpr (S::kDither) {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + k);
+            const uint32_t h = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[k][i] = dithered<S>(g[k][i], h, i);
+        }
+    }
+
+    if (!AA || src == 0) {
+        // The node's own row: slot i (two buffers) or opp(i) (in place,
+        // phase 0), naturally aligned vectors.
+        T *o = out + (int64_t)y * d.rstride + x0;
+        if (x0 + VEC <= d.nx) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                Pack<T, VEC> p;
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
+                store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, p);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                if (x0 + k < d.nx) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        o[(int64_t)(AA ? opp_of(i) : i) * d.dstride + k] = S::from_r(g[k][i]);
+                }
+            }
+        }
+    } else {
+        // In place, phase 1: to the neighbours x + e_i (reflected at walls).
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const Loc w = aa_dest(d, i, y, 1);
+            T *o = out + (int64_t)w.dir * d.dstride + (int64_t)w.row * d.rstride;
+            if (interior) {
+                Pack<T, VEC> p;
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
+                store_pack_loose<T, VEC>(o + x0 + w.dx, p);
+            } else {
+#pragma unroll
+                for (int k = 0; k < VEC; ++k)
+                    if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = S::from_r(g[k][i]);
+            }
+        }
+    }
+}
+
+// ---- kernels ---------------------------------------------------------------
+
+// In place, the phase is a template argument (PH = 0 or 1), so each phase's
+// kernel carries only its own store path and register budget.
+template <int ST, int VEC, int FM, int SCH, bool AA, int PH>
+__global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t ntiles)
+{
+    const int64_t t = xcd_order(blockIdx.x, ntiles);
+    int y, x0;
+    if (decode(d, t, threadIdx.x, y, x0))
+        step_group<ST, VEC, FM, SCH, AA>(d, AA ? PH : src, y, x0);
+}
+
+// One time step of every lattice of a batch whose step count exceeds
+// `substep`.  Persistent: block b takes one contiguous chunk of the tile
+// range of lattices [l_lo, l_hi) (numbered lattice by lattice, row group by
+// row group), so a block walks down the rows of one lattice and on to the
+// next.  The lattices of one launch share storage, force mode, scheme and
+// storage scheme, so the kernel holds a single copy of the node update (and
+// the register budget of the single-lattice kernel).
+template <int ST, int VEC, int FM, int SCH, bool AA>
+__global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats, int l_lo,
+                                                  int l_hi, int64_t ntiles, int substep)
+{
+    const int64_t G = gridDim.x;
+    const int64_t b = xcd_order(blockIdx.x, G);
+    const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
+    if (lo >= hi) return;
+    // Lattice holding tile lo: last j with tile0 <= lo.
+    int a = l_lo, z = l_hi - 1;
+    while (a < z) {
+        const int m = (a + z + 1) >> 1;
+        if (lats[m].tile0 <= lo)
+            a = m;
+        else
+            z = m - 1;
+    }
+    int j = a;
+    for (int64_t t = lo; t < hi; ++t) {
+        while (t >= lats[j].tile0 + lats[j].ntiles) ++j;
+        const LatDesc &d = lats[j];
+        if (substep >= d.steps) continue;
+        const int src = (d.parity + substep) & 1;
+        int y, x0;
+        if (!decode(d, t - d.tile0, threadIdx.x, y, x0)) continue;
+        step_group<ST, VEC, FM, SCH, AA>(d, src, y, x0);
+    }
+}
+
+// ---- dispatch --------------------------------------------------------------
+
+// Kernel key of a lattice: ((in place) * 4 + force mode) * 2 + scheme.
+#define CLBM_STEP_CASE(FM, SCH, AA)                                                        \
+    case (AA * 4 + FM) * 2 + SCH:                                                          \
+        if constexpr (AA) {                                                                \
+            if (src == 1)                                                                  \
+                k_step<ST, VEC, FM, SCH, AA, 1><<<grid, block, lds, s>>>(e, src, ntiles);  \
+            else                                                                           \
+                k_step<ST, VEC, FM, SCH, AA, 0><<<grid, block, lds, s>>>(e, src, ntiles);  \
+        } else {                                                                           \
+            k_step<ST, VEC, FM, SCH, AA, 0><<<grid, block, lds, s>>>(e, src, ntiles);      \
+        }                                                                                  \
+        break;
+#define CLBM_BATCH_CASE(FM, SCH, AA)                                                       \
+    case (AA * 4 + FM) * 2 + SCH:                                                          \
+        k_batch<ST, VEC, FM, SCH, AA><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);  \
+        break;
+#define CLBM_FOR_SCHEMES(CASE, FM, AA) CASE(FM, SCH_CONSISTENT, AA) CASE(FM, SCH_GUO_LBL, AA)
+
+// lds: bytes of dynamic LDS per block, never touched by the kernel; it
+// only limits how many blocks a compute unit holds at once.
+template <int ST, int VEC>
+hipError_t step_dispatch(const LatDesc &d, int src, size_t lds, hipStream_t s)
+{
+    int32_t tpr, rows, segs;
+    int64_t ntiles;
+    tile_geometry(d.nx, d.ny, VEC, &tpr, &rows, &segs, &ntiles);
+    LatDesc e = d;
+    e.tpr = tpr;
+    e.rows = rows;
+    e.segs = segs;
+    e.vec = VEC;
+    const dim3 grid((unsigned)ntiles), block(kBlock);
+    switch (kernel_key(d)) {
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_CONST, false)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_ROW, false)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_FIELD, false)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_SC, false)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_CONST, true)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_ROW, true)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_FIELD, true)
+        CLBM_FOR_SCHEMES(CLBM_STEP_CASE, FM_SC, true)
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Batches never hold Shan-Chen lattices (their force needs a pass of its
+// own before each step).
+template <int ST, int VEC>
+hipError_t batch_dispatch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int grid,
+                          int substep, int key, hipStream_t s)
+{
+    const dim3 g((unsigned)grid), b(kBlock);
+    switch (key) {
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_CONST, false)
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_ROW, false)
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_FIELD, false)
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_CONST, true)
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_ROW, true)
+        CLBM_FOR_SCHEMES(CLBM_BATCH_CASE, FM_FIELD, true)
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#undef CLBM_STEP_CASE
+#undef CLBM_BATCH_CASE
+#undef CLBM_FOR_SCHEMES
+
+// Nodes per thread compiled for each storage type: 2 or 1 (FP64), 4, 2 or
+// 1 (FP32), 8, 4 or 2 (16-bit).
+template <int ST>
+struct VecSet {
+    static constexpr int a = ST == ST_F64 ? 2 : (ST == ST_F32 ? 4 : 8);
+    static constexpr int b = a / 2, c = ST == ST_F64 ? 1 : a / 4;
+};
+
+}  // namespace
+
+template <int ST>
+hipError_t launch_step_st(const LatDesc &d, int src, int vec, size_t lds, hipStream_t s)
+{
+    using V = VecSet<ST>;
+    if (vec == V::a) return step_dispatch<ST, V::a>(d, src, lds, s);
+    if (vec == V::b) return step_dispatch<ST, V::b>(d, src, lds, s);
+    if (vec == V::c && V::c != V::b) return step_dispatch<ST, V::c>(d, src, lds, s);
+    return hipErrorInvalidValue;
+}
+
+template <int ST>
+hipError_t launch_batch_st(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int key,
+                           int vec, int grid, int substep, hipStream_t s)
+{
+    using V = VecSet<ST>;
+    if (vec == V::a) return batch_dispatch<ST, V::a>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
+    if (vec == V::b) return batch_dispatch<ST, V::b>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
+    if (vec == V::c && V::c != V::b)
+        return batch_dispatch<ST, V::c>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace clbm

@@ -1,0 +1,8 @@
+// clbm_step_bf16.hip -- step and batch kernels for BF16 (round to nearest) storage.
+#include "clbm_step.h"
+
+namespace clbm {
+template hipError_t launch_step_st<ST_BF16>(const LatDesc &, int, int, size_t, hipStream_t);
+template hipError_t launch_batch_st<ST_BF16>(const LatDesc *, int, int, int64_t, int, int, int, int,
+                                         hipStream_t);
+}  // namespace clbm

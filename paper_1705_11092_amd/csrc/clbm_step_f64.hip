@@ -1,0 +1,8 @@
+// clbm_step_f64.hip -- step and batch kernels for FP64 storage.
+#include "clbm_step.h"
+
+namespace clbm {
+template hipError_t launch_step_st<ST_F64>(const LatDesc &, int, int, size_t, hipStream_t);
+template hipError_t launch_batch_st<ST_F64>(const LatDesc *, int, int, int64_t, int, int, int, int,
+                                         hipStream_t);
+}  // namespace clbm

@@ -120,11 +120,14 @@ class _Pending:
 
 class GpuBackend:
     """Backend on the HIP library: one clbm.Lattice per request, advanced
-    together by a clbm.Batch rebuilt whenever the set of requests changes."""
+    together by a clbm.Batch rebuilt whenever the set of requests changes.
+    With inplace=True every request streams in place (one buffer instead of
+    two): half the footprint, so twice the requests fit a budget, with
+    bitwise the same results."""
 
     def __init__(self, budget_bytes: Optional[int] = None, budget_frac: float = 0.8,
                  device: str = "cuda", autotune_cache: Optional[str] = None,
-                 rate_lups: float = 6e10):
+                 rate_lups: float = 6e10, inplace: bool = False):
         import torch
 
         from . import clbm
@@ -137,19 +140,21 @@ class GpuBackend:
         self.budget = int(budget_bytes)
         self.autotune_cache = autotune_cache
         self.rate = rate_lups  # for choosing the tick length
+        self.inplace = bool(inplace)
         self._batch = None
         self._members: tuple = ()
 
     def footprint(self, req) -> int:
         wl = req.workload
-        return 2 * self.clbm.buffer_bytes(wl.nx, wl.ny, req.storage)
+        return (1 if self.inplace else 2) * self.clbm.buffer_bytes(wl.nx, wl.ny, req.storage)
 
     def capacity(self) -> int:
         return self.budget
 
     def open(self, req):
         return self.clbm.lattice_from_workload(req.workload, storage=req.storage,
-                                               device=str(self.device), stream=self.stream)
+                                               device=str(self.device), stream=self.stream,
+                                               inplace=self.inplace)
 
     def _ensure_batch(self, slots):
         key = tuple(id(s) for s in slots)

@@ -34,11 +34,11 @@ def oracle_run(wl, steps, scheme=oracle.SCHEME_CONSISTENT, nthreads=0):
     return f, rho, ux, uy
 
 
-def gpu_lattice(wl, storage, scheme="consistent"):
+def gpu_lattice(wl, storage, scheme="consistent", inplace=False):
     from paper_1705_11092_amd import clbm
     lat = clbm.Lattice(wl.nx, wl.ny, wl.s, storage=storage,
                        bc_y="bounceback" if wl.bc_y == 1 else "periodic", rho0=wl.rho0,
-                       scheme=scheme)
+                       scheme=scheme, inplace=inplace)
     if wl.force_kind == "field":
         lat.set_force("field", fx=wl.force_params[0], fy=wl.force_params[1])
     elif wl.force_kind == "none":
@@ -49,8 +49,8 @@ def gpu_lattice(wl, storage, scheme="consistent"):
     return lat
 
 
-def gpu_run(wl, storage, steps, scheme="consistent", graph_steps=None):
-    lat = gpu_lattice(wl, storage, scheme)
+def gpu_run(wl, storage, steps, scheme="consistent", graph_steps=None, inplace=False):
+    lat = gpu_lattice(wl, storage, scheme, inplace=inplace)
     if graph_steps is not None:
         lat.set_graph_steps(graph_steps)
     lat.step(steps)

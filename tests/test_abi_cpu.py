@@ -45,9 +45,10 @@ def test_host_helpers():
 def test_create_rejects_bad_arguments_before_touching_the_gpu():
     from paper_1705_11092_amd import clbm
     h = ctypes.c_void_p()
-    base = dict(nx=8, ny=8, bc_y=0, storage=1, scheme=0, reserved=0, s0=1, s1=1, sb=1, s2=1,
+    base = dict(nx=8, ny=8, bc_y=0, storage=1, scheme=0, streaming=0, s0=1, s1=1, sb=1, s2=1,
                 s3=1, s4=1, rho0=1.0, pop_a=None, pop_b=None, stream=None)
-    bad = [dict(nx=0), dict(bc_y=3), dict(storage=7), dict(scheme=5), dict(reserved=1),
+    bad = [dict(nx=0), dict(bc_y=3), dict(storage=7), dict(scheme=5), dict(streaming=2),
+           dict(streaming=1, pop_b=0x1000),
            dict(s2=0.0), dict(s3=2.5), dict(s4=float("nan")), dict(rho0=-1.0)]
     for change in bad:
         cfg = clbm._Config(**{**base, **change})
@@ -57,4 +58,6 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert clbm.lib.clbm_destroy(None) == clbm.CLBM_OK
     assert clbm.lib.clbm_batch_destroy(None) == clbm.CLBM_OK
     assert clbm.lib.clbm_step(None, 1) == clbm.CLBM_EINVAL
+    assert clbm.lib.clbm_set_occupancy(None, 3) == clbm.CLBM_EINVAL
+    assert clbm.lib.clbm_get_occupancy(None) == -1
     assert clbm.lib.clbm_batch_variant_count() >= 1

@@ -241,6 +241,26 @@ def test_checkpoint_resume(storage):
         lat.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16sr"])
+def test_occupancy_cap_keeps_results(storage):
+    from paper_1705_11092_amd import clbm
+    wl = _case(300, 70, 1, "field", 910)
+    ref = None
+    for occ in (0, 2, 3, 5, 16):
+        lat = gpu_lattice(wl, storage)
+        lat.occupancy = occ
+        assert lat.occupancy == occ
+        lat.step(70)
+        f = lat.get_populations().cpu().numpy()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), f"cap {occ}"
+        for bad in (1, 17, -1):
+            with pytest.raises(clbm.ClbmError):
+                lat.occupancy = bad
+        lat.close()
+
+
 def test_graph_and_direct_launches_agree_bitwise():
     wl = _case(200, 50, 0, "kolmogorov", 600)
     out = []
