@@ -56,6 +56,24 @@ int elem_bytes(int storage)
 // Elements of one direction's run within a lattice row (padded).
 int64_t pitch_of(int nx) { return ((int64_t)nx + clbm::kRowAlign - 1) / clbm::kRowAlign * clbm::kRowAlign; }
 
+// log2 of the rows per row block: double while one direction's run in a
+// block is shorter than kBlockRunBytes and the block stays within the
+// lattice height.
+int row_shift(int nx, int ny, int eb)
+{
+    const int64_t run = pitch_of(nx) * eb;
+    int sh = 0;
+    while (run << sh < clbm::kBlockRunBytes && (2LL << sh) <= ny) ++sh;
+    return sh;
+}
+
+// Rows allocated: ny rounded up to whole row blocks.
+int64_t rows_allocated(int nx, int ny, int eb)
+{
+    const int64_t r = 1LL << row_shift(nx, ny, eb);
+    return (ny + r - 1) / r * r;
+}
+
 constexpr int kStorageKinds = 6;
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
@@ -248,8 +266,8 @@ size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage)
 {
     const int eb = elem_bytes(storage);
     if (nx < 1 || ny < 1 || eb == 0) return 0;
-    if (pitch_of(nx) * (int64_t)ny > (int64_t)INT32_MAX) return 0;
-    return (size_t)(9 * pitch_of(nx) * ny * eb);
+    if (pitch_of(nx) * rows_allocated(nx, ny, eb) > (int64_t)INT32_MAX) return 0;
+    return (size_t)(9 * pitch_of(nx) * rows_allocated(nx, ny, eb) * eb);
 }
 
 int clbm_create(const clbm_config *cfg, clbm_handle **out)
@@ -258,7 +276,8 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     if (!cfg || !out) return fail(CLBM_EINVAL, "cfg and out must not be NULL");
     *out = nullptr;
     if (cfg->nx < 1 || cfg->ny < 1) return fail(CLBM_EINVAL, "nx and ny must be >= 1");
-    if (pitch_of(cfg->nx) * (int64_t)cfg->ny > (int64_t)INT32_MAX)
+    const int eb = elem_bytes(cfg->storage);
+    if (eb && pitch_of(cfg->nx) * rows_allocated(cfg->nx, cfg->ny, eb) > (int64_t)INT32_MAX)
         return fail(CLBM_EINVAL, "lattice too large (nx * ny must stay below 2^31)");
     if (cfg->bc_y != CLBM_Y_PERIODIC && cfg->bc_y != CLBM_Y_BOUNCEBACK)
         return fail(CLBM_EINVAL, "bc_y must be CLBM_Y_PERIODIC or CLBM_Y_BOUNCEBACK");
@@ -287,8 +306,10 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.buf[0] = cfg->pop_a;
     d.buf[1] = inplace ? cfg->pop_a : cfg->pop_b;
     d.inplace = inplace ? 1 : 0;
-    d.dstride = pitch_of(cfg->nx);
-    d.rstride = 9 * pitch_of(cfg->nx);
+    d.rshift = row_shift(cfg->nx, cfg->ny, eb);
+    d.pitch = pitch_of(cfg->nx);
+    d.dstride = d.pitch << d.rshift;
+    d.bstride = 9 * d.dstride;
     d.nx = cfg->nx;
     d.ny = cfg->ny;
     d.bc_y = cfg->bc_y;
@@ -559,14 +580,18 @@ double clbm_s_from_nu(double nu) { return 1.0 / (3.0 * nu + 0.5); }
 namespace {
 
 // Kernel variants of a batch: bytes each thread loads per direction (nodes
-// per thread = bytes / element size, clamped to the compiled set) and
-// persistent blocks per compute unit.
+// per thread = bytes / element size, clamped to the compiled set), the grid
+// (persistent blocks per compute unit, or 0: one block per tile) and a cap
+// on resident blocks per compute unit (0: none, -1: the single-lattice
+// default of the group's storage type for the group's traffic).
 struct Variant {
     int vec_bytes;
     int blocks_per_cu;
+    int cap;
 };
 const Variant kVariants[] = {
-    {16, 8}, {16, 4}, {16, 16}, {8, 8}, {8, 4}, {8, 16}, {4, 8}, {4, 4}, {4, 16},
+    {16, 0, -1}, {16, 0, 0}, {16, 0, 4}, {16, 16, 0}, {8, 0, -1},
+    {8, 0, 0},   {8, 16, 0}, {4, 0, -1}, {4, 0, 0},  {4, 16, 0},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -591,9 +616,14 @@ struct clbm_batch {
     struct Group {
         int storage, key, vec, l_lo, l_hi;  // key = clbm::kernel_key
         int64_t ntiles;
+        int64_t tbase;                // first entry of the group in the tile map
+        size_t lds;                   // dynamic LDS per block enforcing the cap
     };
     std::vector<Group> groups;
     std::vector<LatDesc> tab;         // host copy of the table's geometry
+    int32_t *d_tile_lat = nullptr;    // tile -> lattice map of every group (stream-ordered)
+    int64_t tile_lat_cap = 0;         // entries allocated
+    bool map_dirty = true;            // geometry changed since the map was built
     int variant = 0;
     int cus = 256;
     int chunk = 32;                   // launches per captured graph
@@ -623,6 +653,7 @@ void batch_order(clbm_batch *b)
 void batch_geometry(clbm_batch *b)
 {
     b->groups.clear();
+    int64_t tbase = 0;
     b->tab.assign(b->order.size(), LatDesc());
     size_t pos = 0;
     while (pos < b->order.size()) {
@@ -632,17 +663,23 @@ void batch_geometry(clbm_batch *b)
         const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
         const int lo = (int)pos;
         int64_t tiles = 0;
+        size_t bytes = 0;
         while (pos < b->order.size() && group_key(b->lats[b->order[pos]]->d) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
-            clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.rows, &d.segs, &d.ntiles);
+            clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
             d.vec = vec;
             d.tile0 = tiles;
             tiles += d.ntiles;
+            bytes += 2 * clbm_buffer_bytes(d.nx, d.ny, d.storage);
             b->tab[pos] = d;
             ++pos;
         }
-        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles});
+        const int cap = kVariants[b->variant].cap;
+        const size_t lds = lds_for_occupancy(cap < 0 ? default_occupancy(st, bytes) : cap);
+        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds});
+        tbase += tiles;
     }
+    b->map_dirty = true;
     retire_graph(b->graph, b->stream);
     b->graph = nullptr;
 }
@@ -663,8 +700,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
             LatDesc d = h->d;
             const LatDesc &g = b->tab[pos];
             d.tpr = g.tpr;
-            d.rows = g.rows;
-            d.segs = g.segs;
+            d.inv_tpr = g.inv_tpr;
             d.vec = g.vec;
             d.tile0 = g.tile0;
             d.ntiles = g.ntiles;
@@ -674,6 +710,24 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
             p.d[k] = d;
         }
         HIPCHK(clbm::launch_upload(b->d_lats, first, n, p, b->stream));
+    }
+    if (b->map_dirty) {
+        // Tile -> lattice map of the new geometry.  Graphs that read the old
+        // map were retired with the old geometry; the old map is freed in
+        // stream order behind their launches.
+        const int64_t total = b->groups.empty() ? 0 : b->groups.back().tbase + b->groups.back().ntiles;
+        if (total > b->tile_lat_cap) {
+            if (b->d_tile_lat) HIPCHK(hipFreeAsync(b->d_tile_lat, b->stream));
+            b->d_tile_lat = nullptr;
+            b->tile_lat_cap = 0;
+            HIPCHK(hipMallocAsync(reinterpret_cast<void **>(&b->d_tile_lat),
+                                  sizeof(int32_t) * (size_t)total, b->stream));
+            b->tile_lat_cap = total;
+        }
+        for (const auto &g : b->groups)
+            HIPCHK(clbm::launch_tile_map(b->d_lats, g.l_lo, g.l_hi, g.ntiles, b->d_tile_lat + g.tbase,
+                                         b->stream));
+        b->map_dirty = false;
     }
     return CLBM_OK;
 }
@@ -693,11 +747,12 @@ void batch_refresh(clbm_batch *b)
 
 int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
 {
-    const int64_t grid = (int64_t)b->cus * kVariants[b->variant].blocks_per_cu;
+    const Variant &v = kVariants[b->variant];
+    const int64_t grid = v.blocks_per_cu ? (int64_t)b->cus * v.blocks_per_cu : INT32_MAX;
     for (const auto &g : b->groups) {
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
-        HIPCHK(clbm::launch_batch(b->d_lats, g.l_lo, g.l_hi, g.ntiles, g.storage, g.key, g.vec, gg,
-                                  substep, s));
+        HIPCHK(clbm::launch_batch(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.storage, g.key,
+                                  g.vec, gg, substep, g.lds, s));
     }
     return CLBM_OK;
 }
@@ -933,6 +988,7 @@ int clbm_batch_destroy(clbm_batch *b)
     if (!b) return CLBM_OK;
     retire_graph(b->graph, b->stream);
     if (b->d_lats) (void)hipFreeAsync(b->d_lats, b->stream);
+    if (b->d_tile_lat) (void)hipFreeAsync(b->d_tile_lat, b->stream);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipGetLastError();
     delete b;

@@ -20,6 +20,26 @@ __global__ void k_upload(LatDesc *lats, int first, int n, UploadPayload p)
     if (j < n) lats[first + j] = p.d[j];
 }
 
+// Tile -> lattice map of one batch group: tile t belongs to the last
+// lattice j of [l_lo, l_hi) with tile0 <= t (binary search, once per
+// geometry rather than once per block and step).
+__global__ void k_tile_map(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles,
+                           int32_t *tile_lat)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int a = l_lo, z = l_hi - 1;
+        while (a < z) {
+            const int m = (a + z + 1) >> 1;
+            if (lats[m].tile0 <= t)
+                a = m;
+            else
+                z = m - 1;
+        }
+        tile_lat[t] = a;
+    }
+}
+
 // After a chunk of `chunk` batch launches: advance each lattice's parity by
 // the steps it took and lower its remaining count.
 __global__ void k_batch_advance(LatDesc *lats, int count, int chunk)
@@ -264,10 +284,10 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
     }
 }
 
-hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int storage,
-                        int key, int vec, int grid, int substep, hipStream_t s)
+hipError_t launch_batch(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int storage,
+                        int key, int vec, int grid, int substep, size_t lds, hipStream_t s)
 {
-#define CLBM_B(ST) launch_batch_st<ST>(lats, l_lo, l_hi, ntiles, key, vec, grid, substep, s)
+#define CLBM_B(ST) launch_batch_st<ST>(lats, tile_lat, ntiles, key, vec, grid, substep, lds, s)
     switch (storage) {
     case ST_F64: return CLBM_B(ST_F64);
     case ST_F32: return CLBM_B(ST_F32);
@@ -283,6 +303,14 @@ hipError_t launch_batch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles,
 hipError_t launch_upload(LatDesc *lats, int first, int n, const UploadPayload &p, hipStream_t s)
 {
     k_upload<<<1, 64, 0, s>>>(lats, first, n, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_map(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles,
+                           int32_t *tile_lat, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    k_tile_map<<<helper_blocks(ntiles), kBlock, 0, s>>>(lats, l_lo, l_hi, ntiles, tile_lat);
     return hipGetLastError();
 }
 

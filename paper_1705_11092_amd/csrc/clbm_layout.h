@@ -2,9 +2,13 @@
 // streaming maps of the two storage schemes, and the tile decode shared by
 // the step kernels and the per-node helpers.
 //
-// Layout: row-interleaved.  Lattice row y holds the 9 directions (order of
-// Eq. 1) one after the other, each a run of nx elements padded to a multiple
-// of 8, x fastest: element (slot i, y, x) sits at y * rstride + i * dstride + x.
+// Layout: row blocks.  R = 2^rshift consecutive lattice rows form a block;
+// within it the 9 directions (order of Eq. 1) follow one another, each as R
+// runs of nx elements padded to a multiple of 8 (the pitch), x fastest:
+// element (slot i, y, x) sits at (y / R) bstride + i dstride + (y mod R)
+// pitch + x, with dstride = R pitch and bstride = 9 R pitch.  Wide lattices
+// take R = 1 (each row holds its 9 runs back to back); narrow ones take
+// larger R so that every direction still streams long contiguous pieces.
 //
 // Streaming (Eq. 10) is stored in one of two ways.
 //
@@ -154,6 +158,12 @@ __device__ __forceinline__ Loc aa_dest(const LatDesc &d, int i, int y, int phase
     return w;
 }
 
+// Offset of row y's first element within its block's direction 0.
+__device__ __forceinline__ int64_t row_base(const LatDesc &d, int y)
+{
+    return (int64_t)(y >> d.rshift) * d.bstride + (int64_t)(y & ((1 << d.rshift) - 1)) * d.pitch;
+}
+
 __device__ __forceinline__ int wrap_x(int x, int nx)
 {
     return x < 0 ? x + nx : (x >= nx ? x - nx : x);
@@ -166,19 +176,29 @@ __device__ __forceinline__ T *pre_slot(const LatDesc &d, int src, int i, int x, 
 {
     const Loc s = d.inplace ? aa_source(d, i, y, src) : source_of(d, i, y);
     T *base = static_cast<T *>(d.buf[d.inplace ? 0 : src]);
-    return base + (int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride + wrap_x(x - s.dx, d.nx);
+    return base + (int64_t)s.dir * d.dstride + row_base(d, s.row) + wrap_x(x - s.dx, d.nx);
 }
 
-// Decode tile t of a lattice for thread tid: row y, first node x0.
+// Decode tile t of a lattice for thread tid: group g = t kBlock + tid is
+// row y = g / tpr, first node x0 = (g mod tpr) vec.  The quotient comes from
+// a double product (exact to within one for g < 2^31) and is corrected.
 __device__ __forceinline__ bool decode(const LatDesc &d, int64_t t, int tid, int &y, int &x0)
 {
-    const int rg = (int)(t / d.segs);
-    const int seg = (int)(t - (int64_t)rg * d.segs);
-    const int r = tid / d.tpr;
-    const int c = tid - r * d.tpr;
-    y = rg * d.rows + r;
-    x0 = (seg * d.tpr + c) * d.vec;
-    return r < d.rows && y < d.ny && x0 < d.nx;
+    const int64_t g64 = t * kBlock + tid;
+    if (g64 >= (int64_t)d.ny * d.tpr) return false;
+    const int g = (int)g64;
+    int q = (int)((double)g * d.inv_tpr);
+    int r = g - q * d.tpr;
+    if (r < 0) {
+        --q;
+        r += d.tpr;
+    } else if (r >= d.tpr) {
+        ++q;
+        r -= d.tpr;
+    }
+    y = q;
+    x0 = r * d.vec;
+    return true;
 }
 
 }  // namespace

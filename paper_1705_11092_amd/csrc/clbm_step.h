@@ -54,7 +54,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const Loc s = AA ? aa_source(d, i, y, src) : source_of(d, i, y);
-        rowp[i] = in + (int64_t)s.dir * d.dstride + (int64_t)s.row * d.rstride;
+        rowp[i] = in + (int64_t)s.dir * d.dstride + row_base(d, s.row);
         dxs[i] = s.dx;
     }
 
@@ -96,32 +96,24 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 
     if (!AA || src == 0) {
         // The node's own row: slot i (two buffers) or opp(i) (in place,
-        // phase 0), naturally aligned vectors.
-        T *o = out + (int64_t)y * d.rstride + x0;
-        if (x0 + VEC <= d.nx) {
+        // phase 0), naturally aligned vectors.  Groups reaching past nx
+        // write their padding elements too (copies of the last node's
+        // values; never read), so every cache line of a row is written
+        // whole.
+        T *o = out + row_base(d, y) + x0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                Pack<T, VEC> p;
+        for (int i = 0; i < 9; ++i) {
+            Pack<T, VEC> p;
 #pragma unroll
-                for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
-                store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, p);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                if (x0 + k < d.nx) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        o[(int64_t)(AA ? opp_of(i) : i) * d.dstride + k] = S::from_r(g[k][i]);
-                }
-            }
+            for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
+            store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, p);
         }
     } else {
         // In place, phase 1: to the neighbours x + e_i (reflected at walls).
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const Loc w = aa_dest(d, i, y, 1);
-            T *o = out + (int64_t)w.dir * d.dstride + (int64_t)w.row * d.rstride;
+            T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
             if (interior) {
                 Pack<T, VEC> p;
 #pragma unroll
@@ -132,6 +124,16 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
                 for (int k = 0; k < VEC; ++k)
                     if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = S::from_r(g[k][i]);
             }
+        }
+        if (x0 + VEC > d.nx) {
+            // No node's value lands in the padding of this row in this
+            // phase: fill it, so its cache lines are written whole.
+            T *o = out + row_base(d, y);
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+#pragma unroll
+                for (int k = 0; k < VEC; ++k)
+                    if (x0 + k >= d.nx) o[(int64_t)i * d.dstride + x0 + k] = S::from_r(R(0));
         }
     }
 }
@@ -150,30 +152,23 @@ __global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t nti
 }
 
 // One time step of every lattice of a batch whose step count exceeds
-// `substep`.  Persistent: block b takes one contiguous chunk of the tile
-// range of lattices [l_lo, l_hi) (numbered lattice by lattice, row group by
-// row group), so a block walks down the rows of one lattice and on to the
-// next.  The lattices of one launch share storage, force mode, scheme and
+// `substep`.  Block b takes one contiguous chunk of the group's tiles
+// (numbered lattice by lattice, row by row): one tile per block with a grid
+// of one block per tile, or a persistent walk down the rows of one lattice
+// and on to the next with a smaller grid.  tile_lat names the lattice of
+// each tile.  The lattices of one launch share storage, force mode, scheme and
 // storage scheme, so the kernel holds a single copy of the node update (and
 // the register budget of the single-lattice kernel).
 template <int ST, int VEC, int FM, int SCH, bool AA>
-__global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats, int l_lo,
-                                                  int l_hi, int64_t ntiles, int substep)
+__global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ lats,
+                                                  const int32_t *__restrict__ tile_lat,
+                                                  int64_t ntiles, int substep)
 {
     const int64_t G = gridDim.x;
     const int64_t b = xcd_order(blockIdx.x, G);
     const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
     if (lo >= hi) return;
-    // Lattice holding tile lo: last j with tile0 <= lo.
-    int a = l_lo, z = l_hi - 1;
-    while (a < z) {
-        const int m = (a + z + 1) >> 1;
-        if (lats[m].tile0 <= lo)
-            a = m;
-        else
-            z = m - 1;
-    }
-    int j = a;
+    int j = tile_lat[lo];  // lattice holding tile lo
     for (int64_t t = lo; t < hi; ++t) {
         while (t >= lats[j].tile0 + lats[j].ntiles) ++j;
         const LatDesc &d = lats[j];
@@ -201,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ la
         break;
 #define CLBM_BATCH_CASE(FM, SCH, AA)                                                       \
     case (AA * 4 + FM) * 2 + SCH:                                                          \
-        k_batch<ST, VEC, FM, SCH, AA><<<g, b, 0, s>>>(lats, l_lo, l_hi, ntiles, substep);  \
+        k_batch<ST, VEC, FM, SCH, AA><<<g, b, lds, s>>>(lats, tile_lat, ntiles, substep);   \
         break;
 #define CLBM_FOR_SCHEMES(CASE, FM, AA) CASE(FM, SCH_CONSISTENT, AA) CASE(FM, SCH_GUO_LBL, AA)
 
@@ -210,13 +205,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const LatDesc *__restrict__ la
 template <int ST, int VEC>
 hipError_t step_dispatch(const LatDesc &d, int src, size_t lds, hipStream_t s)
 {
-    int32_t tpr, rows, segs;
-    int64_t ntiles;
-    tile_geometry(d.nx, d.ny, VEC, &tpr, &rows, &segs, &ntiles);
     LatDesc e = d;
-    e.tpr = tpr;
-    e.rows = rows;
-    e.segs = segs;
+    int64_t ntiles;
+    tile_geometry(d.nx, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
     e.vec = VEC;
     const dim3 grid((unsigned)ntiles), block(kBlock);
     switch (kernel_key(d)) {
@@ -237,8 +228,8 @@ hipError_t step_dispatch(const LatDesc &d, int src, size_t lds, hipStream_t s)
 // Batches never hold Shan-Chen lattices (their force needs a pass of its
 // own before each step).
 template <int ST, int VEC>
-hipError_t batch_dispatch(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int grid,
-                          int substep, int key, hipStream_t s)
+hipError_t batch_dispatch(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int grid,
+                          int substep, int key, size_t lds, hipStream_t s)
 {
     const dim3 g((unsigned)grid), b(kBlock);
     switch (key) {
@@ -279,14 +270,15 @@ hipError_t launch_step_st(const LatDesc &d, int src, int vec, size_t lds, hipStr
 }
 
 template <int ST>
-hipError_t launch_batch_st(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles, int key,
-                           int vec, int grid, int substep, hipStream_t s)
+hipError_t launch_batch_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
+                           int vec, int grid, int substep, size_t lds, hipStream_t s)
 {
     using V = VecSet<ST>;
-    if (vec == V::a) return batch_dispatch<ST, V::a>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
-    if (vec == V::b) return batch_dispatch<ST, V::b>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
-    if (vec == V::c && V::c != V::b)
-        return batch_dispatch<ST, V::c>(lats, l_lo, l_hi, ntiles, grid, substep, key, s);
+#define CLBM_BD(V_) batch_dispatch<ST, V_>(lats, tile_lat, ntiles, grid, substep, key, lds, s)
+    if (vec == V::a) return CLBM_BD(V::a);
+    if (vec == V::b) return CLBM_BD(V::b);
+    if (vec == V::c && V::c != V::b) return CLBM_BD(V::c);
+#undef CLBM_BD
     return hipErrorInvalidValue;
 }
 

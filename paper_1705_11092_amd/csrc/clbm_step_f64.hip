@@ -3,6 +3,6 @@
 
 namespace clbm {
 template hipError_t launch_step_st<ST_F64>(const LatDesc &, int, int, size_t, hipStream_t);
-template hipError_t launch_batch_st<ST_F64>(const LatDesc *, int, int, int64_t, int, int, int, int,
-                                         hipStream_t);
+template hipError_t launch_batch_st<ST_F64>(const LatDesc *, const int32_t *, int64_t, int, int,
+                                         int, int, size_t, hipStream_t);
 }  // namespace clbm
