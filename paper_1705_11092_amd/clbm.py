@@ -114,7 +114,11 @@ def _field(a, shape, device) -> Optional[torch.Tensor]:
     """FP64 contiguous device tensor of `shape` from numpy / torch / None."""
     if a is None:
         return None
-    t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+    if not isinstance(a, torch.Tensor):
+        a = np.asarray(a, dtype=np.float64)
+        if not a.flags.writeable:  # e.g. a broadcast view: torch wants its own copy
+            a = a.copy()
+    t = torch.as_tensor(a)
     t = t.to(device=device, dtype=torch.float64).contiguous()
     if tuple(t.shape) != tuple(shape):
         raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
