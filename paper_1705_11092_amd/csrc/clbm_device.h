@@ -95,33 +95,53 @@ template <> struct Storage<ST_BF16> {
 // Stochastically rounded 16-bit storage.  A value that changes by a few
 // units in the last place per step (a slowly evolving flow, a small body
 // force) is rounded the same way step after step by round-to-nearest, a
-// drift that accumulates.  Here each stored value v is rounded to nearest
-// after adding a uniform dither of one 16-bit ulp, r - 1/2 with r in
-// [0, 1): the result is the lower or upper neighbour of v with
-// probabilities that make it exact on average.  r comes from a hash of the
-// node index and the node's own FP32 values, so it is deterministic (a
-// lattice gives the same bits alone or in any batch, in any launch shape)
-// and changes from step to step with the state.
+// drift that accumulates.  Here each stored value v becomes its lower or
+// upper 16-bit neighbour with probabilities that make it exact on average:
+// gfx950's stochastic-rounding conversions (v_cvt_sr_f16_f32,
+// v_cvt_sr_bf16_f32) round up when the discarded fraction of v plus a
+// uniform random fraction, taken from the high bits of a 32-bit operand,
+// reaches one ulp (measured on MI355X: P(up) equals the fraction for both
+// types, signs round by magnitude, binary16 subnormals are unbiased).  The
+// operand comes from a hash of the node index and the node's own FP32
+// values, so it is deterministic (a lattice gives the same bits alone or in
+// any batch, in any launch shape) and changes from step to step with the
+// state.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bfloat2_t __attribute__((ext_vector_type(2)));
+
 template <> struct Storage<ST_F16_SR> {
     using T = _Float16;
     using R = float;
     static constexpr bool kDither = true;
-    // ulp = 2^(e - 11) for v = m 2^e, m in [0.5, 1), down to the
-    // binary16 subnormal spacing 2^-24.
-    static constexpr int kUlpShift = 11;
-    static constexpr int kUlpMin = -24;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
     static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }
+    static __device__ __forceinline__ T from_r_sr(R v, uint32_t rnd)
+    {
+        return __builtin_amdgcn_cvt_sr_f16_f32(half2_t{}, v, rnd, false)[0];
+    }
+    // Two values into the low and high halves of one register.
+    static __device__ __forceinline__ half2_t from_r_sr2(R a, uint32_t ra, R b, uint32_t rb)
+    {
+        return __builtin_amdgcn_cvt_sr_f16_f32(
+            __builtin_amdgcn_cvt_sr_f16_f32(half2_t{}, a, ra, false), b, rb, true);
+    }
 };
 
 template <> struct Storage<ST_BF16_SR> {
     using T = __bf16;
     using R = float;
     static constexpr bool kDither = true;
-    static constexpr int kUlpShift = 8;
-    static constexpr int kUlpMin = -126;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
     static __device__ __forceinline__ T from_r(R v) { return (__bf16)v; }
+    static __device__ __forceinline__ T from_r_sr(R v, uint32_t rnd)
+    {
+        return __builtin_amdgcn_cvt_sr_bf16_f32(bfloat2_t{}, v, rnd, false)[0];
+    }
+    static __device__ __forceinline__ bfloat2_t from_r_sr2(R a, uint32_t ra, R b, uint32_t rb)
+    {
+        return __builtin_amdgcn_cvt_sr_bf16_f32(
+            __builtin_amdgcn_cvt_sr_bf16_f32(bfloat2_t{}, a, ra, false), b, rb, true);
+    }
 };
 
 // 32-bit integer finaliser (xor-shift-multiply, as in MurmurHash3's fmix32
@@ -136,17 +156,13 @@ __device__ __forceinline__ uint32_t hash32(uint32_t h)
     return h;
 }
 
-// v plus a dither of (r - 1/2) ulp, r from 24 bits of (h * odd_i); zero
-// stays zero.  The caller rounds the result to nearest.
-template <typename S>
-__device__ __forceinline__ float dithered(float v, uint32_t h, int i)
+// Random operand of population i of a node with hash h: a Weyl step of
+// the golden-ratio increment, so each direction's operand is uniform
+// (h is) and the nine of a node spread evenly over [0, 2^32).  One add per
+// value, where a multiply would cost four.
+__device__ __forceinline__ uint32_t sr_operand(uint32_t h, int i)
 {
-    const uint32_t r = (h * (2u * (uint32_t)i + 0x2545f491u)) >> 8;
-    int e = __builtin_amdgcn_frexp_expf(v) - S::kUlpShift;
-    e = e < S::kUlpMin ? S::kUlpMin : e;
-    const float ulp = __uint_as_float((uint32_t)(e + 127) << 23);
-    const float d = ((float)r * (1.0f / 16777216.0f) - 0.5f) * ulp;
-    return v != 0.0f ? v + d : v;
+    return h + (uint32_t)i * 0x9e3779b9u;
 }
 
 // ---- relaxation parameters in the arithmetic type --------------------------

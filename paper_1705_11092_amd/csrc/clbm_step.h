@@ -84,14 +84,32 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         collide<R, SCH>(g[k], Fx, Fy, rt);
     }
 
+    // Every value in its storage type: rounded to nearest, or
+    // stochastically with a per-node hash of the node index and its values.
+    Pack<T, VEC> q[9];
     if constexpr (S::kDither) {
+        uint32_t h[VEC];
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + k);
-            const uint32_t h = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[k][i] = dithered<S>(g[k][i], h, i);
+            h[k] = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
         }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+#pragma unroll
+            for (int k = 0; k + 1 < VEC; k += 2) {
+                const auto two = S::from_r_sr2(g[k][i], sr_operand(h[k], i), g[k + 1][i],
+                                               sr_operand(h[k + 1], i));
+                q[i].v[k] = two[0];
+                q[i].v[k + 1] = two[1];
+            }
+            if constexpr (VEC % 2) q[i].v[VEC - 1] = S::from_r_sr(g[VEC - 1][i], sr_operand(h[VEC - 1], i));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) q[i].v[k] = S::from_r(g[k][i]);
     }
 
     if (!AA || src == 0) {
@@ -102,12 +120,8 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         // whole.
         T *o = out + row_base(d, y) + x0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            Pack<T, VEC> p;
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
-            store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, p);
-        }
+        for (int i = 0; i < 9; ++i)
+            store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, q[i]);
     } else {
         // In place, phase 1: to the neighbours x + e_i (reflected at walls).
 #pragma unroll
@@ -115,14 +129,11 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
             const Loc w = aa_dest(d, i, y, 1);
             T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
             if (interior) {
-                Pack<T, VEC> p;
-#pragma unroll
-                for (int k = 0; k < VEC; ++k) p.v[k] = S::from_r(g[k][i]);
-                store_pack_loose<T, VEC>(o + x0 + w.dx, p);
+                store_pack_loose<T, VEC>(o + x0 + w.dx, q[i]);
             } else {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k)
-                    if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = S::from_r(g[k][i]);
+                    if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = q[i].v[k];
             }
         }
         if (x0 + VEC > d.nx) {
