@@ -10,7 +10,7 @@ Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
 algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
 oracle's throughput on the host cores for a bounded sample of the same
 workload.  Beside it, in the same line: the same lattice streamed in place
-(one buffer), the same lattice with 16-bit storage, the batch of 256 uneven Kolmogorov lattices advanced by one
+(one buffer), the same lattice with FP64 and 16-bit storage, the batch of 256 uneven Kolmogorov lattices advanced by one
 persistent launch per step, and a served Poisson stream of solves with its
 p50/p99 latency.
 
@@ -299,7 +299,7 @@ def main():
             "mlups": round(m, 1), "ms_per_step": round(msi / args.steps, 5),
             "hbm_frac": round(m * 1e6 * bpl / 8e12, 4),
             "footprint_bytes": nodes * bpl // 2}
-        for st in ("f16", "bf16", "f16sr", "bf16sr"):
+        for st in ("f64", "f16", "bf16", "f16sr", "bf16sr"):
             ms16, _, _ = run_gpu(args.n, st, args.steps, args.warmup)
             m = nodes / (ms16 / args.steps / 1e3) / 1e6
             extra[st] = {"mlups": round(m, 1), "ms_per_step": round(ms16 / args.steps, 5),
