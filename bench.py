@@ -10,7 +10,8 @@ Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
 algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
 oracle's throughput on the host cores for a bounded sample of the same
 workload.  Beside it, in the same line: the same lattice streamed in place
-(one buffer), the same lattice with FP64 and 16-bit storage, the batch of 256 uneven Kolmogorov lattices advanced by one
+(one buffer), the same lattice with FP64 and 16-bit storage, the 64 x 32
+Poiseuille channel and the cache-resident 1024^2 lattice, the batch of 256 uneven Kolmogorov lattices advanced by one
 persistent launch per step, and a served Poisson stream of solves with its
 p50/p99 latency.
 
@@ -90,6 +91,42 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False
     _, _, _, tot = lat.moments(fields=False)
     lat.close()
     return ms, wall, tot
+
+
+def run_small():
+    """The two small workloads: the 64 x 32 Poiseuille channel (FP64, 10,000
+    steps from rest, launch-bound: microseconds per step through graphs)
+    and the 1024^2 Taylor-Green lattice (FP64 and FP32, 2,000 steps; its
+    two buffers fit the 256 MB Infinity Cache, so its bandwidth is a
+    cache-resident figure, not HBM)."""
+    import torch
+    from paper_1705_11092_amd import clbm, inputs
+
+    def timed(lat, steps):
+        lat.step(steps // 10)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(lat.stream)
+        lat.step(steps)
+        t1.record(lat.stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) * 1e3 / steps
+
+    out = {}
+    wl = inputs.poiseuille(64, 32, Fx=1e-6, tau=1.0, steps=10_000)
+    lat = clbm.lattice_from_workload(wl, storage="f64")
+    out["poiseuille_64x32_f64"] = {"us_per_step": round(timed(lat, 10_000), 3), "steps": 10_000}
+    lat.close()
+    for st in ("f64", "f32"):
+        wl = inputs.taylor_green(1024, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=2000)
+        lat = clbm.lattice_from_workload(wl, storage=st)
+        us = timed(lat, 2000)
+        lat.close()
+        out[f"taylor_green_1024_{st}"] = {
+            "us_per_step": round(us, 3), "mlups": round(1024 * 1024 / us, 1),
+            "gb_s_cache_resident": round(BYTES_PER_LUP[st] * 1024 * 1024 / us / 1e3, 1)}
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batch(steps: int, warmup: int, count: int = 256):
@@ -305,6 +342,7 @@ def main():
             extra[st] = {"mlups": round(m, 1), "ms_per_step": round(ms16 / args.steps, 5),
                          "hbm_frac": round(m * 1e6 * BYTES_PER_LUP[st] / 8e12, 4)}
         extra["batch"] = run_batch(1000, 20)
+        extra.update(run_small())
         if args.serve_requests > 0:
             extra["served"] = run_served(args.serve_requests)
         line["also"] = extra
