@@ -207,7 +207,8 @@ int clbm_set_populations(clbm_handle *h, const double *f);
 int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
 
 /* Cap on the step kernel's resident blocks per compute unit (0 = none, or
- * 2..16), enforced with unused LDS per block.  Results do not depend on it.
+ * 2..16), enforced with unused LDS per block, for clbm_step (a batch takes
+ * its caps from its variant).  Results do not depend on it.
  * The default comes from measurements on MI355X: lattices whose step
  * traffic exceeds the 256 MB Infinity Cache stream HBM fastest with 3
  * blocks per CU for FP32 and 2 for FP64 (4 for cache-resident FP64); the
