@@ -216,6 +216,18 @@ int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
 int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu);
 int32_t clbm_get_occupancy(const clbm_handle *h); /* -1 for NULL */
 
+/* Small lattices step in a resident kernel: one block of 1024 threads that
+ * holds the whole lattice and runs up to 4096 steps per launch with a
+ * barrier between steps, instead of one launch per step (tiny lattices are
+ * otherwise bound by launch overhead).  It applies when the lattice has at
+ * most max_groups groups of nodes (ny x padded nx / nodes per thread, 2
+ * nodes per thread for FP64 and 4 otherwise; default 512, the measured
+ * break-even on MI355X: one compute unit does all the work, so larger
+ * lattices step faster as graphed launches), nsteps >= 2 and the force is
+ * not Shan-Chen.  0 disables it; the limit is at most 2^20.  Results are
+ * bitwise the same either way.  Errors: CLBM_EINVAL. */
+int clbm_set_resident_limit(clbm_handle *h, int64_t max_groups);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *clbm_last_error(void);
 

@@ -60,6 +60,7 @@ def _load():
         "clbm_init": (ctypes.c_int, [vp, vp, vp, vp]),
         "clbm_step": (ctypes.c_int, [vp, i64]),
         "clbm_set_occupancy": (ctypes.c_int, [vp, i32]),
+        "clbm_set_resident_limit": (ctypes.c_int, [vp, i64]),
         "clbm_get_occupancy": (i32, [vp]),
         "clbm_step_count": (i64, [vp]),
         "clbm_moments": (ctypes.c_int, [vp, vp, vp, vp, dp]),
@@ -93,7 +94,7 @@ EXPORTED = (
     "clbm_buffer_bytes", "clbm_create", "clbm_destroy", "clbm_set_force", "clbm_init",
     "clbm_step", "clbm_step_count", "clbm_moments", "clbm_error_norms",
     "clbm_get_populations", "clbm_set_populations", "clbm_set_graph_steps",
-    "clbm_set_occupancy", "clbm_get_occupancy",
+    "clbm_set_occupancy", "clbm_get_occupancy", "clbm_set_resident_limit",
     "clbm_last_error", "clbm_nonslip_s3", "clbm_s_from_nu", "clbm_batch_create",
     "clbm_batch_step", "clbm_batch_step_each", "clbm_batch_autotune",
     "clbm_batch_variant_count", "clbm_batch_set_variant", "clbm_batch_get_variant",
@@ -218,6 +219,12 @@ class Lattice:
 
     def set_graph_steps(self, n: int):
         _check(lib.clbm_set_graph_steps(self._h, int(n)))
+
+    def set_resident_limit(self, max_groups: int):
+        """Largest lattice (in groups of nodes) stepped by the resident
+        kernel; 0 turns it off."""
+        _check(lib.clbm_set_resident_limit(self._h, int(max_groups)))
+        return self
 
     @property
     def occupancy(self) -> int:

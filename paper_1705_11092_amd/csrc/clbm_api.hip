@@ -216,6 +216,7 @@ struct clbm_handle {
     double *d_out = nullptr;     // reduced totals on the device
     int vec = 4;
     int occ = 0;                 // blocks per compute unit of the step kernel (0: no cap)
+    int64_t resident_max = clbm::kResidentMaxGroups;  // resident kernel up to this many groups
     size_t lds = 0;              // dynamic LDS per block that enforces occ
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -452,6 +453,19 @@ int clbm_step(clbm_handle *h, int64_t nsteps)
     int rc = need_ready(h);
     if (rc) return rc;
     if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
+    const int rvec = h->d.storage == CLBM_F64 ? 2 : 4;
+    const int64_t groups = (int64_t)h->d.ny * (pitch_of(h->d.nx) / rvec);
+    if (nsteps >= 2 && h->d.force_mode != clbm::FM_SC && groups <= h->resident_max) {
+        // A small lattice: many steps per launch in one resident block.
+        for (int64_t left = nsteps; left > 0;) {
+            const int n = (int)std::min<int64_t>(left, 4096);
+            HIPCHK(clbm::launch_resident(h->d, h->parity, n, h->stream));
+            h->parity = (h->parity + n) & 1;
+            left -= n;
+        }
+        h->steps += nsteps;
+        return CLBM_OK;
+    }
     int64_t left = nsteps;
     while (left > 0) {
         if (h->graph_steps > 0 && left >= h->graph_steps) {
@@ -566,6 +580,16 @@ int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu)
 }
 
 int32_t clbm_get_occupancy(const clbm_handle *h) { return h ? h->occ : -1; }
+
+int clbm_set_resident_limit(clbm_handle *h, int64_t max_groups)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (max_groups < 0 || max_groups > (int64_t)1 << 20)
+        return fail(CLBM_EINVAL, "resident limit must lie in [0, 2^20] groups");
+    h->resident_max = max_groups;
+    return CLBM_OK;
+}
 
 const char *clbm_last_error(void) { return g_err.c_str(); }
 

@@ -17,6 +17,15 @@ enum ForceMode {
 // Threads per block of every step kernel.
 constexpr int kBlock = 256;
 
+// The resident kernel: one block of kResidentBlock threads keeps a small
+// lattice and runs many steps in one launch.  Its step time grows with the
+// lattice (one compute unit does all the work); on MI355X it beats graphed
+// single-step launches up to about 512 groups of nodes (16 x 16: 1.9 against
+// 3.1 us per step; 64 x 32 FP32: 4.0 against 5.1) and loses beyond (64 x 32
+// FP64, 1024 groups: 5.5 against 4.5), hence the default limit.
+constexpr int kResidentBlock = 1024;
+constexpr int kResidentMaxGroups = 512;
+
 // Row padding: each direction's row starts on a multiple of kRowAlign
 // elements so that the vector stores of every storage type are naturally
 // aligned.
@@ -102,7 +111,12 @@ hipError_t launch_batch(const LatDesc *lats, const int32_t *tile_lat, int64_t nt
 // tile0 / ntiles fields.
 hipError_t launch_tile_map(const LatDesc *lats, int l_lo, int l_hi, int64_t ntiles,
                            int32_t *tile_lat, hipStream_t s);
+// nsteps steps of a small lattice (no Shan-Chen force) in one launch of one
+// block; vec is the storage type's default nodes per thread.
+hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s);
 // The same per storage type, one translation unit each (clbm_step_*.hip).
+template <int ST>
+hipError_t launch_resident_st(const LatDesc &d, int src, int nsteps, hipStream_t s);
 template <int ST>
 hipError_t launch_step_st(const LatDesc &d, int src, int vec, size_t lds, hipStream_t s);
 template <int ST>

@@ -284,6 +284,19 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
     }
 }
 
+hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)
+{
+    switch (d.storage) {
+    case ST_F64: return launch_resident_st<ST_F64>(d, src, nsteps, s);
+    case ST_F32: return launch_resident_st<ST_F32>(d, src, nsteps, s);
+    case ST_F16: return launch_resident_st<ST_F16>(d, src, nsteps, s);
+    case ST_BF16: return launch_resident_st<ST_BF16>(d, src, nsteps, s);
+    case ST_F16_SR: return launch_resident_st<ST_F16_SR>(d, src, nsteps, s);
+    case ST_BF16_SR: return launch_resident_st<ST_BF16_SR>(d, src, nsteps, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batch(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int storage,
                         int key, int vec, int grid, int substep, size_t lds, hipStream_t s)
 {

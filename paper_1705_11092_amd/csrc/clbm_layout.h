@@ -53,45 +53,72 @@ struct VecTypes {
     typedef T tight __attribute__((ext_vector_type(N)));
 };
 
-template <typename T, int N>
+// Vector accesses are non-temporal (NT = true: every value is used once per
+// step and streams through HBM) or ordinary (the resident kernel, whose
+// small lattice stays in the caches and whose waves must see each other's
+// stores through the compute unit's in-order memory path).  The pointer
+// casts stay inside each function so that the element-aligned `loose` type
+// keeps its alignment.
+template <typename T, int N, bool NT = true>
 __device__ __forceinline__ Pack<T, N> load_pack(const T *p)
 {
     Pack<T, N> r;
     if constexpr (N == 1) {
-        r.v[0] = __builtin_nontemporal_load(p);
+        if constexpr (NT)
+            r.v[0] = __builtin_nontemporal_load(p);
+        else
+            r.v[0] = *p;
     } else {
-        const typename VecTypes<T, N>::loose v =
-            __builtin_nontemporal_load(reinterpret_cast<const typename VecTypes<T, N>::loose *>(p));
+        const typename VecTypes<T, N>::loose *q = reinterpret_cast<const typename VecTypes<T, N>::loose *>(p);
+        typename VecTypes<T, N>::loose v;
+        if constexpr (NT)
+            v = __builtin_nontemporal_load(q);
+        else
+            v = *q;
 #pragma unroll
         for (int k = 0; k < N; ++k) r.v[k] = v[k];
     }
     return r;
 }
 
-template <typename T, int N>
+template <typename T, int N, bool NT = true>
 __device__ __forceinline__ void store_pack(T *p, const Pack<T, N> &v)
 {
     if constexpr (N == 1) {
-        __builtin_nontemporal_store(v.v[0], p);
+        if constexpr (NT)
+            __builtin_nontemporal_store(v.v[0], p);
+        else
+            *p = v.v[0];
     } else {
         typename VecTypes<T, N>::tight a;
 #pragma unroll
         for (int k = 0; k < N; ++k) a[k] = v.v[k];
-        __builtin_nontemporal_store(a, reinterpret_cast<typename VecTypes<T, N>::tight *>(p));
+        typename VecTypes<T, N>::tight *q = reinterpret_cast<typename VecTypes<T, N>::tight *>(p);
+        if constexpr (NT)
+            __builtin_nontemporal_store(a, q);
+        else
+            *q = a;
     }
 }
 
 // Store of N elements that may start one element off a vector boundary.
-template <typename T, int N>
+template <typename T, int N, bool NT = true>
 __device__ __forceinline__ void store_pack_loose(T *p, const Pack<T, N> &v)
 {
     if constexpr (N == 1) {
-        __builtin_nontemporal_store(v.v[0], p);
+        if constexpr (NT)
+            __builtin_nontemporal_store(v.v[0], p);
+        else
+            *p = v.v[0];
     } else {
         typename VecTypes<T, N>::loose a;
 #pragma unroll
         for (int k = 0; k < N; ++k) a[k] = v.v[k];
-        __builtin_nontemporal_store(a, reinterpret_cast<typename VecTypes<T, N>::loose *>(p));
+        typename VecTypes<T, N>::loose *q = reinterpret_cast<typename VecTypes<T, N>::loose *>(p);
+        if constexpr (NT)
+            __builtin_nontemporal_store(a, q);
+        else
+            *q = a;
     }
 }
 
@@ -179,12 +206,11 @@ __device__ __forceinline__ T *pre_slot(const LatDesc &d, int src, int i, int x, 
     return base + (int64_t)s.dir * d.dstride + row_base(d, s.row) + wrap_x(x - s.dx, d.nx);
 }
 
-// Decode tile t of a lattice for thread tid: group g = t kBlock + tid is
-// row y = g / tpr, first node x0 = (g mod tpr) vec.  The quotient comes from
-// a double product (exact to within one for g < 2^31) and is corrected.
-__device__ __forceinline__ bool decode(const LatDesc &d, int64_t t, int tid, int &y, int &x0)
+// Decode group g64 of a lattice: row y = g / tpr, first node
+// x0 = (g mod tpr) vec.  The quotient comes from a double product (exact to
+// within one for g < 2^31) and is corrected.
+__device__ __forceinline__ bool decode_group(const LatDesc &d, int64_t g64, int &y, int &x0)
 {
-    const int64_t g64 = t * kBlock + tid;
     if (g64 >= (int64_t)d.ny * d.tpr) return false;
     const int g = (int)g64;
     int q = (int)((double)g * d.inv_tpr);
@@ -199,6 +225,12 @@ __device__ __forceinline__ bool decode(const LatDesc &d, int64_t t, int tid, int
     y = q;
     x0 = r * d.vec;
     return true;
+}
+
+// Decode tile t of a lattice for thread tid: group t kBlock + tid.
+__device__ __forceinline__ bool decode(const LatDesc &d, int64_t t, int tid, int &y, int &x0)
+{
+    return decode_group(d, t * kBlock + tid, y, x0);
 }
 
 }  // namespace

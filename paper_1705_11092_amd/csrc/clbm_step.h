@@ -8,7 +8,8 @@
 // them in registers and stores the post-collision values; every stored
 // value is read exactly once per step, so there is no reuse for LDS to
 // capture: the step is bound by HBM traffic, 2 x 9 values per node.  Loads
-// and stores are non-temporal.
+// and stores are non-temporal, except in the resident kernel for tiny
+// lattices, whose state stays in the caches.
 #pragma once
 
 #include "clbm_device.h"
@@ -40,7 +41,7 @@ __device__ __forceinline__ Rates<R> rates_of(const LatDesc &d)
 // AA = true: in place, src is the phase; read buf[0], write buf[1] (the same
 // buffer, except for the batch autotuner's timed launches, which send the
 // writes to scratch memory).
-template <int ST, int VEC, int FM, int SCH, bool AA>
+template <int ST, int VEC, int FM, int SCH, bool AA, bool NT = true>
 __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int x0)
 {
     using S = Storage<ST>;
@@ -63,7 +64,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
     if (interior) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const Pack<T, VEC> p = load_pack<T, VEC>(rowp[i] + x0 - dxs[i]);
+            const Pack<T, VEC> p = load_pack<T, VEC, NT>(rowp[i] + x0 - dxs[i]);
 #pragma unroll
             for (int k = 0; k < VEC; ++k) g[k][i] = S::to_r(p.v[k]);
         }
@@ -121,7 +122,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         T *o = out + row_base(d, y) + x0;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            store_pack<T, VEC>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, q[i]);
+            store_pack<T, VEC, NT>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, q[i]);
     } else {
         // In place, phase 1: to the neighbours x + e_i (reflected at walls).
 #pragma unroll
@@ -129,7 +130,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
             const Loc w = aa_dest(d, i, y, 1);
             T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
             if (interior) {
-                store_pack_loose<T, VEC>(o + x0 + w.dx, q[i]);
+                store_pack_loose<T, VEC, NT>(o + x0 + w.dx, q[i]);
             } else {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k)
@@ -160,6 +161,28 @@ __global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t nti
     int y, x0;
     if (decode(d, t, threadIdx.x, y, x0))
         step_group<ST, VEC, FM, SCH, AA>(d, AA ? PH : src, y, x0);
+}
+
+// nsteps steps of one small lattice by one block: the block sweeps every
+// group of the lattice, then every wave waits until its own loads and
+// stores have completed, meets the others at a barrier, and goes on to the
+// next step, which reads what this one wrote.  All waves share one compute
+// unit and its L1, and the accesses are ordinary (not non-temporal), so the
+// stores are visible to the other waves after the barrier.  For lattices
+// whose step is otherwise a few microseconds of launch overhead.
+template <int ST, int VEC, int FM, int SCH, bool AA>
+__global__ __launch_bounds__(kResidentBlock) void k_resident(LatDesc d, int src, int nsteps)
+{
+    const int64_t total = (int64_t)d.ny * d.tpr;
+    for (int s = 0; s < nsteps; ++s) {
+        const int phase = (src + s) & 1;
+        for (int64_t g = threadIdx.x; g < total; g += kResidentBlock) {
+            int y, x0;
+            if (decode_group(d, g, y, x0)) step_group<ST, VEC, FM, SCH, AA, false>(d, phase, y, x0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
 }
 
 // One time step of every lattice of a batch whose step count exceeds
@@ -256,6 +279,32 @@ hipError_t batch_dispatch(const LatDesc *lats, const int32_t *tile_lat, int64_t 
     return hipGetLastError();
 }
 
+#define CLBM_RESIDENT_CASE(FM, SCH, AA)                                                    \
+    case (AA * 4 + FM) * 2 + SCH:                                                          \
+        k_resident<ST, VEC, FM, SCH, AA><<<1, kResidentBlock, 0, s>>>(e, src, nsteps);     \
+        break;
+
+template <int ST, int VEC>
+hipError_t resident_dispatch(const LatDesc &d, int src, int nsteps, hipStream_t s)
+{
+    LatDesc e = d;
+    int64_t ntiles;
+    tile_geometry(d.nx, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
+    e.vec = VEC;
+    switch (kernel_key(d)) {
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_CONST, false)
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_ROW, false)
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_FIELD, false)
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_CONST, true)
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_ROW, true)
+        CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_FIELD, true)
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#undef CLBM_RESIDENT_CASE
 #undef CLBM_STEP_CASE
 #undef CLBM_BATCH_CASE
 #undef CLBM_FOR_SCHEMES
@@ -278,6 +327,14 @@ hipError_t launch_step_st(const LatDesc &d, int src, int vec, size_t lds, hipStr
     if (vec == V::b) return step_dispatch<ST, V::b>(d, src, lds, s);
     if (vec == V::c && V::c != V::b) return step_dispatch<ST, V::c>(d, src, lds, s);
     return hipErrorInvalidValue;
+}
+
+// The resident kernel runs at the storage type's default nodes per thread.
+template <int ST>
+hipError_t launch_resident_st(const LatDesc &d, int src, int nsteps, hipStream_t s)
+{
+    constexpr int vec = ST == ST_F64 ? 2 : 4;
+    return resident_dispatch<ST, vec>(d, src, nsteps, s);
 }
 
 template <int ST>

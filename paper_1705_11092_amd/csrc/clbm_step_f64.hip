@@ -3,6 +3,7 @@
 
 namespace clbm {
 template hipError_t launch_step_st<ST_F64>(const LatDesc &, int, int, size_t, hipStream_t);
+template hipError_t launch_resident_st<ST_F64>(const LatDesc &, int, int, hipStream_t);
 template hipError_t launch_batch_st<ST_F64>(const LatDesc *, const int32_t *, int64_t, int, int,
                                          int, int, size_t, hipStream_t);
 }  // namespace clbm

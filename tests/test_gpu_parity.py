@@ -241,6 +241,37 @@ def test_checkpoint_resume(storage):
         lat.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "f16sr", "bf16sr"])
+@pytest.mark.parametrize("inplace", [False, True])
+def test_resident_kernel_matches_step_kernel(storage, inplace):
+    # Small lattices run many steps per launch in one resident block; the
+    # node arithmetic is the step kernel's, so the results are bitwise equal.
+    # Fixed rates and a small velocity amplitude keep these white-noise
+    # states stable over 79 steps (random rates near 2 can make them
+    # diverge in exact arithmetic); FP64 is also held to the oracle.
+    small = [(37, 23, 0, "field"), (64, 32, 1, "const"), (1, 17, 1, "const"), (19, 1, 0, "field"),
+             (2, 2, 0, "field"), (96, 20, 1, "kolmogorov")]
+    rates = (1.0, 1.2, 1.25, 1.25, 1.1, 1.1)
+    for k, (nx, ny, bc, force) in enumerate(small):
+        wl = inputs.random_state(nx, ny, seed=920 + k, bc_y=bc, force=force, amp_f=1e-3,
+                                 amp_u=0.02, s=rates)
+        out = []
+        for limit in (2048, 0):
+            lat = gpu_lattice(wl, storage, inplace=inplace)
+            lat.set_resident_limit(limit)
+            lat.step(77)
+            lat.step(2)
+            rho, ux, uy, tot = lat.moments()
+            out.append((lat.get_populations().cpu().numpy(), rho.cpu().numpy(), ux.cpu().numpy()))
+            lat.close()
+        assert np.isfinite(out[0][0]).all()
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a, b), f"{nx}x{ny} {storage} in place {inplace}"
+        if storage == "f64":
+            fo, _, _, _ = oracle_run(wl, 79)
+            assert np.max(np.abs(out[0][0] - fo)) <= 1e-12, f"{nx}x{ny} against the oracle"
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16sr"])
 def test_occupancy_cap_keeps_results(storage):
     from paper_1705_11092_amd import clbm
