@@ -267,6 +267,13 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
         assert np.isfinite(out[0][0]).all()
         for a, b in zip(out[0], out[1]):
             assert np.array_equal(a, b), f"{nx}x{ny} {storage} in place {inplace}"
+        if k == 0:
+            from paper_1705_11092_amd import clbm
+            lat = gpu_lattice(wl, storage, inplace=inplace)
+            for bad in (-1, 2**20 + 1):
+                with pytest.raises(clbm.ClbmError):
+                    lat.set_resident_limit(bad)
+            lat.close()
         if storage == "f64":
             fo, _, _, _ = oracle_run(wl, 79)
             assert np.max(np.abs(out[0][0] - fo)) <= 1e-12, f"{nx}x{ny} against the oracle"
