@@ -59,6 +59,14 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         dxs[i] = s.dx;
     }
 
+    // The force first: for the table-driven modes its loads then overlap
+    // the population loads below instead of waiting behind them (the two
+    // load paths are separate branches, and nothing is scheduled across
+    // their join).
+    R Fx[VEC], Fy[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) force_at<R, FM>(d, x0 + k < d.nx ? x0 + k : d.nx - 1, y, Fx[k], Fy[k]);
+
     const bool interior = x0 >= 1 && x0 + VEC < d.nx;
     R g[VEC][9];
     if (interior) {
@@ -79,11 +87,7 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 
     const Rates<R> rt = rates_of<R>(d);
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-        R Fx, Fy;
-        force_at<R, FM>(d, x0 + k < d.nx ? x0 + k : d.nx - 1, y, Fx, Fy);
-        collide<R, SCH>(g[k], Fx, Fy, rt);
-    }
+    for (int k = 0; k < VEC; ++k) collide<R, SCH>(g[k], Fx[k], Fy[k], rt);
 
     // Every value in its storage type: rounded to nearest, or
     // stochastically with a per-node hash of the node index and its values.
