@@ -119,7 +119,9 @@ typedef struct {
 /* Bytes each of pop_a and pop_b must hold for this lattice and storage:
  * 9 populations per node, each row padded to a multiple of 8 elements and
  * the height rounded up to whole row blocks (narrow lattices group up to
- * 2^k rows per block).  The layout inside is the library's; use
+ * 2^k rows per block), plus 64 spare bytes at the end (the step's vector
+ * loads may reach one element past the last row).  The layout inside is
+ * the library's; use
  * clbm_get_populations / clbm_set_populations to read or write the state.
  * Returns 0 for invalid arguments. */
 size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage);

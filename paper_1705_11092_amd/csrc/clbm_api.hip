@@ -268,7 +268,7 @@ size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage)
     const int eb = elem_bytes(storage);
     if (nx < 1 || ny < 1 || eb == 0) return 0;
     if (pitch_of(nx) * rows_allocated(nx, ny, eb) > (int64_t)INT32_MAX) return 0;
-    return (size_t)(9 * pitch_of(nx) * rows_allocated(nx, ny, eb) * eb);
+    return (size_t)(9 * pitch_of(nx) * rows_allocated(nx, ny, eb) * eb + clbm::kTailGuardBytes);
 }
 
 int clbm_create(const clbm_config *cfg, clbm_handle **out)

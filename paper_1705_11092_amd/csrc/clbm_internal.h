@@ -26,6 +26,11 @@ constexpr int kBlock = 256;
 constexpr int kResidentBlock = 1024;
 constexpr int kResidentMaxGroups = 512;
 
+// Spare bytes at the end of every population buffer: a step's vector loads
+// may reach one element past the last run (its lane is discarded), and
+// must stay inside the allocation.
+constexpr int64_t kTailGuardBytes = 64;
+
 // Row padding: each direction's row starts on a multiple of kRowAlign
 // elements so that the vector stores of every storage type are naturally
 // aligned.

@@ -29,7 +29,10 @@
 //     a wall it writes slot opp(i) at x: the reflected population).
 // In both phases every location a node reads is written by that same node
 // and no other, so a step is free of races between threads without any
-// ordering between them.
+// ordering between them.  (A thread's vector loads at the ends of a row
+// also touch one element beyond its own, in the neighbouring run or the
+// padding; those lanes are discarded, so a concurrent write there changes
+// nothing.)
 #pragma once
 
 #include "clbm_device.h"

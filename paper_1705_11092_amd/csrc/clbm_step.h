@@ -59,31 +59,47 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         dxs[i] = s.dx;
     }
 
-    // The force first: for the table-driven modes its loads then overlap
-    // the population loads below instead of waiting behind them (the two
-    // load paths are separate branches, and nothing is scheduled across
-    // their join).
+    // The force first: for the table-driven modes its loads then issue
+    // together with the population loads below instead of after them.
     R Fx[VEC], Fy[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) force_at<R, FM>(d, x0 + k < d.nx ? x0 + k : d.nx - 1, y, Fx[k], Fy[k]);
 
-    const bool interior = x0 >= 1 && x0 + VEC < d.nx;
+    // Every group loads its nine runs as vectors starting at x0 - dx.  Such
+    // a vector may reach one element before or after its run: into the
+    // neighbouring run, or, for the last run of the buffer (slot 8, pulled
+    // with dx >= 0 but read at x + 1 by the in-place phase 1), into the
+    // buffer's tail guard; slot 0 starts the buffer and is always read with
+    // dx = 0.  Only the x-periodic wraps take a wrong element: the row's
+    // first node for dx = +1 (its source is x = nx - 1) and its last node
+    // for dx = -1 (source x = 0).  Their sources, the row's last element for
+    // the directions with e_x = +1 and its first for e_x = -1, are loaded
+    // for every group (in bounds whatever the row) ahead of the vectors,
+    // into registers of their own, and selected once everything has
+    // arrived: a branch around these loads would end in a merge that waits
+    // for them before the vectors issue.  Lanes past nx are padding: what
+    // they load is never stored.
+    const int kl = d.nx - 1 - x0;  // lane of the row's last node, if in this group
+    const bool wrap_first = x0 == 0, wrap_last = kl >= 0 && kl < VEC;
+    T raw[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (ex_of(i) != 0) raw[i] = rowp[i][ex_of(i) == 1 ? d.nx - 1 : 0];
     R g[VEC][9];
-    if (interior) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const Pack<T, VEC> p = load_pack<T, VEC, NT>(rowp[i] + x0 - dxs[i]);
+    for (int i = 0; i < 9; ++i) {
+        const Pack<T, VEC> p = load_pack<T, VEC, NT>(rowp[i] + x0 - dxs[i]);
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) g[k][i] = S::to_r(p.v[k]);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-            const int x = x0 + k < d.nx ? x0 + k : d.nx - 1;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[k][i] = S::to_r(rowp[i][wrap_x(x - dxs[i], d.nx)]);
-        }
+        for (int k = 0; k < VEC; ++k) g[k][i] = S::to_r(p.v[k]);
     }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (ex_of(i) == 1 && wrap_first && dxs[i] == 1) g[0][i] = S::to_r(raw[i]);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            if (ex_of(i) == -1 && wrap_last && k == kl && dxs[i] == -1) g[k][i] = S::to_r(raw[i]);
+    }
+    const bool interior = x0 >= 1 && x0 + VEC < d.nx;
 
     const Rates<R> rt = rates_of<R>(d);
 #pragma unroll
@@ -120,9 +136,18 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
     if (!AA || src == 0) {
         // The node's own row: slot i (two buffers) or opp(i) (in place,
         // phase 0), naturally aligned vectors.  Groups reaching past nx
-        // write their padding elements too (copies of the last node's
-        // values; never read), so every cache line of a row is written
-        // whole.
+        // write their padding elements too, so every cache line of a row is
+        // written whole: copies of the row's last node (zeros in a group
+        // wholly inside the padding), never read.
+        if (x0 + VEC > d.nx) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (x0 >= d.nx) q[i].v[0] = S::from_r(R(0));
+#pragma unroll
+                for (int k = 1; k < VEC; ++k)
+                    if (x0 + k >= d.nx) q[i].v[k] = q[i].v[k - 1];
+            }
+        }
         T *o = out + row_base(d, y) + x0;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -158,8 +183,14 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 
 // In place, the phase is a template argument (PH = 0 or 1), so each phase's
 // kernel carries only its own store path and register budget.
+// Waves per SIMD the compiler must leave room for: 5 for the 16-bit storage
+// types at up to 4 nodes per thread (at most 96 VGPRs) except the in-place
+// phase 1 (it would spill), else no demand.
+template <int ST, int VEC, bool AA, int PH>
+constexpr int min_waves() { return (sizeof(typename Storage<ST>::T) == 2 && VEC <= 4 && !(AA && PH == 1)) ? 5 : 1; }
+
 template <int ST, int VEC, int FM, int SCH, bool AA, int PH>
-__global__ __launch_bounds__(kBlock) void k_step(LatDesc d, int src, int64_t ntiles)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<ST, VEC, AA, PH>()))) void k_step(LatDesc d, int src, int64_t ntiles)
 {
     const int64_t t = xcd_order(blockIdx.x, ntiles);
     int y, x0;
