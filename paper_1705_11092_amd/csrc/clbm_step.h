@@ -35,6 +35,26 @@ __device__ __forceinline__ Rates<R> rates_of(const LatDesc &d)
     return rt;
 }
 
+// The value v of the lane below (up = true: lane - 1) or above (lane + 1)
+// in the wave; a lane without such a neighbour gets its own v back.
+template <typename T>
+__device__ __forceinline__ T lane_shift(T v, bool up)
+{
+    static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) == 8, "element size");
+    if constexpr (sizeof(T) == 8) {
+        long long b;
+        __builtin_memcpy(&b, &v, 8);
+        b = up ? __shfl_up(b, 1) : __shfl_down(b, 1);
+        __builtin_memcpy(&v, &b, 8);
+    } else {
+        int b = 0;
+        __builtin_memcpy(&b, &v, sizeof(T));
+        b = up ? __shfl_up(b, 1) : __shfl_down(b, 1);
+        __builtin_memcpy(&v, &b, sizeof(T));
+    }
+    return v;
+}
+
 // ---- the fused step on VEC consecutive nodes of one row -------------------
 
 // AA = false: two buffers, read buffer src, write buffer src ^ 1.
@@ -99,7 +119,6 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         for (int k = 0; k < VEC; ++k)
             if (ex_of(i) == -1 && wrap_last && k == kl && dxs[i] == -1) g[k][i] = S::to_r(raw[i]);
     }
-    const bool interior = x0 >= 1 && x0 + VEC < d.nx;
 
     const Rates<R> rt = rates_of<R>(d);
 #pragma unroll
@@ -153,17 +172,83 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
         for (int i = 0; i < 9; ++i)
             store_pack<T, VEC, NT>(o + (int64_t)(AA ? opp_of(i) : i) * d.dstride, q[i]);
     } else {
-        // In place, phase 1: to the neighbours x + e_i (reflected at walls).
+        // In place, phase 1: node x's value goes to slot w.dir at x + w.dx
+        // (w.dx = e_x, or 0 beyond a wall).
+        if constexpr (sizeof(T) >= 4) {
+            // 4- and 8-byte elements: for w.dx = +1 a lane whose left
+            // neighbour group sits in the adjacent lane of the same row stores
+            // one aligned vector at x0: that neighbour's last value, then its
+            // own first VEC - 1.  Its own last value belongs to the next lane's
+            // vector, or, where the next lane stores none, is stored alone.
+            // w.dx = -1 is the mirror image.  Everything else goes element by
+            // element, so every location has one writer.  (The location a lane
+            // fills with its neighbour's value is read in this phase by that
+            // neighbour alone, whose loads have completed: the value stored
+            // depends on them.)
+            const int lane = __lane_id();
+            const bool real_all = x0 + VEC <= d.nx;
+            const bool plus_vec = lane > 0 && x0 >= VEC && real_all;
+            const bool plus_next = lane < 63 && x0 + 2 * VEC <= d.nx;
+            const bool minus_vec = lane < 63 && x0 + VEC < d.nx;
+            const bool minus_prev = lane > 0 && x0 >= VEC && x0 < d.nx;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const Loc w = aa_dest(d, i, y, 1);
-            T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
-            if (interior) {
-                store_pack_loose<T, VEC, NT>(o + x0 + w.dx, q[i]);
-            } else {
+            for (int i = 0; i < 9; ++i) {
+                const Loc w = aa_dest(d, i, y, 1);
+                T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
+                if (w.dx == 0) {
+                    if (real_all) {
+                        store_pack<T, VEC, NT>(o + x0, q[i]);
+                    } else {
 #pragma unroll
-                for (int k = 0; k < VEC; ++k)
-                    if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = q[i].v[k];
+                        for (int k = 0; k < VEC; ++k)
+                            if (x0 + k < d.nx) o[x0 + k] = q[i].v[k];
+                    }
+                } else if (w.dx == 1) {
+                    const T from_left = lane_shift<T>(q[i].v[VEC - 1], true);
+                    if (plus_vec) {
+                        Pack<T, VEC> p;
+                        p.v[0] = from_left;
+#pragma unroll
+                        for (int k = 1; k < VEC; ++k) p.v[k] = q[i].v[k - 1];
+                        store_pack<T, VEC, NT>(o + x0, p);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k + 1 < VEC; ++k)
+                            if (x0 + k < d.nx) o[wrap_x(x0 + k + 1, d.nx)] = q[i].v[k];
+                    }
+                    if (x0 + VEC - 1 < d.nx && !plus_next) o[wrap_x(x0 + VEC, d.nx)] = q[i].v[VEC - 1];
+                } else {
+                    const T from_right = lane_shift<T>(q[i].v[0], false);
+                    if (minus_vec) {
+                        Pack<T, VEC> p;
+#pragma unroll
+                        for (int k = 0; k + 1 < VEC; ++k) p.v[k] = q[i].v[k + 1];
+                        p.v[VEC - 1] = from_right;
+                        store_pack<T, VEC, NT>(o + x0, p);
+                    } else {
+#pragma unroll
+                        for (int k = 1; k < VEC; ++k)
+                            if (x0 + k < d.nx) o[wrap_x(x0 + k - 1, d.nx)] = q[i].v[k];
+                    }
+                    if (x0 < d.nx && !minus_prev) o[wrap_x(x0 - 1, d.nx)] = q[i].v[0];
+                }
+            }
+        } else {
+            // 16-bit elements: one element-aligned vector per direction for
+            // groups clear of the row ends (their 8-byte stores cost less
+            // than the lane shuffles), element by element otherwise.
+            const bool interior = x0 >= 1 && x0 + VEC < d.nx;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const Loc w = aa_dest(d, i, y, 1);
+                T *o = out + (int64_t)w.dir * d.dstride + row_base(d, w.row);
+                if (interior) {
+                    store_pack_loose<T, VEC, NT>(o + x0 + w.dx, q[i]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k)
+                        if (x0 + k < d.nx) o[wrap_x(x0 + k + w.dx, d.nx)] = q[i].v[k];
+                }
             }
         }
         if (x0 + VEC > d.nx) {
