@@ -35,6 +35,7 @@ CASES = [
     (2, 2, 0, "field"),
     (257, 130, 0, "none"),
     (520, 3, 1, "kolmogorov"),
+    (256, 12, 1, "field"),  # rows of exactly one wave of groups at 4 nodes per thread
 ]
 
 
