@@ -47,10 +47,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_tg4096.json")
 
 
 def kernel_hash() -> str:
+    """Hash of the step kernel's sources with comments and whitespace removed,
+    so that the stored counters stay valid exactly as long as the code does."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -20,9 +20,9 @@ constexpr int kBlock = 256;
 // The resident kernel: one block of kResidentBlock threads keeps a small
 // lattice and runs many steps in one launch.  Its step time grows with the
 // lattice (one compute unit does all the work); on MI355X it beats graphed
-// single-step launches up to about 512 groups of nodes (16 x 16: 1.9 against
-// 3.1 us per step; 64 x 32 FP32: 4.0 against 5.1) and loses beyond (64 x 32
-// FP64, 1024 groups: 5.5 against 4.5), hence the default limit.
+// single-step launches up to about 512 groups of nodes (16 x 16: 1.7 against
+// 3.0 us per step; 64 x 32 FP32: 3.5 against 4.2) and loses beyond (64 x 32
+// FP64, 1024 groups: 4.9 against 4.0), hence the default limit.
 constexpr int kResidentBlock = 1024;
 constexpr int kResidentMaxGroups = 512;
 
