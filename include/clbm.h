@@ -214,7 +214,10 @@ int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
  * The default comes from measurements on MI355X: lattices whose step
  * traffic exceeds the 256 MB Infinity Cache stream HBM fastest with 3
  * blocks per CU for FP32 and 2 for FP64 (4 for cache-resident FP64); the
- * 16-bit kernels run uncapped.  Errors: CLBM_EINVAL. */
+ * 16-bit kernels run uncapped.  In place, such FP32 and FP64 lattices
+ * default to 2 for the phase-0 steps and 3 for phase 1; clbm_get_occupancy
+ * reports the phase-1 cap, and a cap set here applies to both phases.
+ * Errors: CLBM_EINVAL. */
 int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu);
 int32_t clbm_get_occupancy(const clbm_handle *h); /* -1 for NULL */
 

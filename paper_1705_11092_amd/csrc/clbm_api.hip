@@ -87,12 +87,15 @@ bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s <= 2.0; }
 // (196 us against 208 us uncapped at 4096^2), FP64 at 2 (376 against 397);
 // the 16-bit kernels, co-limited by ALU issue, want every wave they can get.
 // Cache-resident lattices: FP64 gains a little at 4, the rest at no cap.
-int default_occupancy(int storage, size_t bytes_per_step)
+// In place (phase 0 all aligned, phase 1 at the neighbours), per-phase
+// sweeps at 4096^2 put phase 0 at 2 for both wide types (FP32 198 us against
+// 202 at 3) and phase 1 at 3 (FP64 392 against 406 at 2).
+int default_occupancy(int storage, size_t bytes_per_step, bool inplace = false, int phase = 1)
 {
     const bool hbm = bytes_per_step > ((size_t)256 << 20);
     switch (storage) {
-    case CLBM_F64: return hbm ? 2 : 4;
-    case CLBM_F32: return hbm ? 3 : 0;
+    case CLBM_F64: return hbm ? (inplace ? (phase == 0 ? 2 : 3) : 2) : 4;
+    case CLBM_F32: return hbm ? (inplace && phase == 0 ? 2 : 3) : 0;
     default: return 0;
     }
 }
@@ -218,6 +221,7 @@ struct clbm_handle {
     int occ = 0;                 // blocks per compute unit of the step kernel (0: no cap)
     int64_t resident_max = clbm::kResidentMaxGroups;  // resident kernel up to this many groups
     size_t lds = 0;              // dynamic LDS per block that enforces occ
+    size_t lds0 = 0;             // the same for in-place phase-0 steps
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -232,6 +236,10 @@ void drop_graphs(clbm_handle *h)
     }
 }
 
+// Dynamic LDS of a step launch from state `src` (the in-place phase 0 has
+// its own default cap).
+size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0 ? h->lds0 : h->lds; }
+
 int build_graph(clbm_handle *h, int parity)
 {
     hipGraph_t g = nullptr;
@@ -239,7 +247,7 @@ int build_graph(clbm_handle *h, int parity)
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
-        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, h->lds, h->cap);
+        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, step_lds(h, (parity + k) & 1), h->cap);
     hipError_t ce = hipStreamEndCapture(h->cap, &g);
     if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -326,8 +334,9 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.h3 = 1.0 - 0.5 * cfg->s3;
     d.h2 = 1.0 - 0.5 * cfg->s2;
     h->vec = default_vec(cfg->storage);
-    h->occ = default_occupancy(cfg->storage, 2 * need);
+    h->occ = default_occupancy(cfg->storage, 2 * need, inplace, 1);
     h->lds = lds_for_occupancy(h->occ);
+    h->lds0 = inplace ? lds_for_occupancy(default_occupancy(cfg->storage, 2 * need, true, 0)) : h->lds;
 
     reap_retired();
     const int nb = clbm::moments_blocks((int64_t)cfg->nx * cfg->ny);
@@ -473,7 +482,7 @@ int clbm_step(clbm_handle *h, int64_t nsteps)
             HIPCHK(hipGraphLaunch(h->graph[h->parity], h->stream));
             left -= h->graph_steps;  // even, so the parity is unchanged
         } else {
-            HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, h->lds, h->stream));
+            HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, step_lds(h, h->parity), h->stream));
             h->parity ^= 1;
             left -= 1;
         }
@@ -575,7 +584,7 @@ int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu)
         return fail(CLBM_EINVAL, "blocks per compute unit must be 0 (no cap) or in [2, 16]");
     drop_graphs(h);
     h->occ = blocks_per_cu;
-    h->lds = lds_for_occupancy(blocks_per_cu);
+    h->lds = h->lds0 = lds_for_occupancy(blocks_per_cu);
     return CLBM_OK;
 }
 
