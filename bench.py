@@ -3,13 +3,16 @@
 Workload: the decaying Taylor-Green vortex plus a uniform body force
 (Fx, Fy) = (1e-6, 5e-7) on a periodic 4096 x 4096 lattice, u0 = 0.01,
 nu = 0.01, populations stored as FP32 deviations f_i - w_i rho0, FP32
-arithmetic.  A step is one fused collide-and-stream launch over the whole
-lattice (Eqs. 9-15).  Inputs are resident in HBM before timing starts.
+arithmetic.  A step is one collide-and-stream update of the whole lattice
+(Eqs. 9-15); the library advances this lattice two fused steps per launch
+(step n + 1 on a tile and its halo kept in LDS, step n + 2 from there).
+Inputs are resident in HBM before timing starts.
 
-Prints one JSON line: MLUPS, the HBM roofline of the step kernel (72
-algorithmic bytes per node update: 9 loads + 9 stores of 4 bytes) and the
-oracle's throughput on the host cores for a bounded sample of the same
-workload.  Beside it, in the same line: the same lattice streamed in place
+Prints one JSON line: MLUPS, the HBM roofline of the two-step kernel (per
+launch the state is read and written once: 72 algorithmic bytes per node
+for two node updates) and the oracle's throughput on the host cores for a
+bounded sample of the same workload.  Beside it, in the same line: the same
+lattice one step per launch (72 bytes per node update), the same lattice streamed in place
 (one buffer), the same lattice with FP64 and 16-bit storage, the 64 x 32
 Poiseuille channel and the cache-resident 1024^2 lattice, the batch of 256 uneven Kolmogorov lattices advanced by one
 persistent launch per step, and a served Poisson stream of solves with its
@@ -38,6 +41,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_LUP = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36, "f16sr": 36, "bf16sr": 36}
 KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_step_f32.hip",
+                  "paper_1705_11092_amd/csrc/clbm_step2.h",
                   "paper_1705_11092_amd/csrc/clbm_step.h",
                   "paper_1705_11092_amd/csrc/clbm_layout.h",
                   "paper_1705_11092_amd/csrc/clbm_force.h",
@@ -75,12 +79,15 @@ def measured_traffic(storage: str, n_nodes: int):
     return t.get("hbm_bytes_per_launch")
 
 
-def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False):
+def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False,
+            pairs: bool = True):
     import torch
     from paper_1705_11092_amd import clbm, inputs
 
     wl = inputs.taylor_green(n, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=steps)
     lat = clbm.lattice_from_workload(wl, storage=storage, inplace=inplace)
+    lat.step_pairs = pairs
+    run_gpu.pairs = lat.step_pairs
     stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -126,11 +133,13 @@ def run_small():
     for st in ("f64", "f32"):
         wl = inputs.taylor_green(1024, u0=0.01, nu=0.01, F=(1e-6, 5e-7), steps=2000)
         lat = clbm.lattice_from_workload(wl, storage=st)
+        per_launch = 2 if lat.step_pairs else 1
         us = timed(lat, 2000)
         lat.close()
         out[f"taylor_green_1024_{st}"] = {
             "us_per_step": round(us, 3), "mlups": round(1024 * 1024 / us, 1),
-            "gb_s_cache_resident": round(BYTES_PER_LUP[st] * 1024 * 1024 / us / 1e3, 1)}
+            "steps_per_launch": per_launch,
+            "gb_s_cache_resident": round(BYTES_PER_LUP[st] * 1024 * 1024 / per_launch / us / 1e3, 1)}
     torch.cuda.empty_cache()
     return out
 
@@ -218,7 +227,7 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     the summary bench.py reports as roofline.traffic."""
     import statistics
     csvs = [os.path.join(d, "run_counter_collection.csv") for d in dirs]
-    step = "k_step<1, 4, 0, 0, false, 0>"
+    step = "k_step2<1, 0, 0>"
     fetch = _counter_values(csvs[0], step, "FETCH_SIZE")
     write = _counter_values(csvs[1], step, "WRITE_SIZE")
     cf = statistics.median(_counter_values(csvs[2], "copyBuffer", "FETCH_SIZE"))
@@ -229,10 +238,10 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     wr = statistics.median(write) * 1024.0 * ws
     alg = BYTES_PER_LUP["f32"] * n * n
     base = "rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 bench.py {a}"
-    step_args = "--steps 5 --warmup 0 --no-cpu-baseline --no-extra"
+    step_args = "--steps 6 --warmup 0 --no-cpu-baseline --no-extra"
     copy_args = f"--calibrate-copy {copy_bytes}"
     out = {
-        "kernel": "clbm::k_step<1, 4, 0, 0, false, 0> (FP32 deviations, 4 nodes per thread, constant "
+        "kernel": "clbm::k_step2<1, 0, 0> (two fused steps per launch; FP32 deviations, constant "
                   "force, consistent scheme)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),
@@ -305,12 +314,17 @@ def main():
         sys.exit(2)
 
     ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup)
+    pairs = run_gpu.pairs
     nodes = args.n * args.n
     ms_step = ms / args.steps
     mlups = nodes / (ms_step / 1e3) / 1e6
     bpl = BYTES_PER_LUP[args.storage]
-    achieved = bpl * nodes / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(args.storage, nodes)
+    # The dominant kernel's launch: two steps (reading and writing the state
+    # once) with pairs, one step otherwise; bytes per launch bpl * nodes.
+    steps_per_launch = 2 if pairs else 1
+    ms_launch = ms_step * steps_per_launch
+    achieved = bpl * nodes / (ms_launch / 1e3) / 1e9
+    traffic = measured_traffic(args.storage, nodes) if pairs else None
     line = {
         "metric": "MLUPS (D2Q9 CLBM step, consistent forcing)",
         "value": round(mlups, 1),
@@ -326,16 +340,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"taylor_green_{args.n}x{args.n}_uniform_force",
                    "storage": f"{args.storage} deviations f_i - w_i rho0",
-                   "nodes": nodes, "bytes_per_lup": bpl, "boundary": "periodic",
+                   "nodes": nodes, "steps_per_launch": steps_per_launch,
+                   "hbm_bytes_per_lup": bpl / steps_per_launch, "boundary": "periodic",
                    "u0": 0.01, "nu": 0.01, "F": [1e-6, 5e-7]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "kernel": "k_step2 (two fused steps per launch)" if pairs else "k_step",
+                     "algorithmic_bytes_per_launch": bpl * nodes,
+                     "ms_per_launch": round(ms_launch, 5)},
         "wall_s": round(wall, 4),
         "mass_total": tot[0],
     }
     if not args.no_extra:
         extra = {}
+        ms1, _, _ = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=False)
+        m = nodes / (ms1 / args.steps / 1e3) / 1e6
+        extra[f"{args.storage}_one_step_per_launch"] = {
+            "mlups": round(m, 1), "ms_per_step": round(ms1 / args.steps, 5),
+            "hbm_frac": round(m * 1e6 * bpl / 8e12, 4)}
         msi, _, _ = run_gpu(args.n, args.storage, args.steps, args.warmup, inplace=True)
         m = nodes / (msi / args.steps / 1e3) / 1e6
         extra[f"{args.storage}_in_place"] = {

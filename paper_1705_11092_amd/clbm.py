@@ -61,6 +61,8 @@ def _load():
         "clbm_step": (ctypes.c_int, [vp, i64]),
         "clbm_set_occupancy": (ctypes.c_int, [vp, i32]),
         "clbm_set_resident_limit": (ctypes.c_int, [vp, i64]),
+        "clbm_set_step_pairs": (ctypes.c_int, [vp, i32]),
+        "clbm_get_step_pairs": (i32, [vp]),
         "clbm_get_occupancy": (i32, [vp]),
         "clbm_step_count": (i64, [vp]),
         "clbm_moments": (ctypes.c_int, [vp, vp, vp, vp, dp]),
@@ -95,6 +97,7 @@ EXPORTED = (
     "clbm_step", "clbm_step_count", "clbm_moments", "clbm_error_norms",
     "clbm_get_populations", "clbm_set_populations", "clbm_set_graph_steps",
     "clbm_set_occupancy", "clbm_get_occupancy", "clbm_set_resident_limit",
+    "clbm_set_step_pairs", "clbm_get_step_pairs",
     "clbm_last_error", "clbm_nonslip_s3", "clbm_s_from_nu", "clbm_batch_create",
     "clbm_batch_step", "clbm_batch_step_each", "clbm_batch_autotune",
     "clbm_batch_variant_count", "clbm_batch_set_variant", "clbm_batch_get_variant",
@@ -225,6 +228,15 @@ class Lattice:
         kernel; 0 turns it off."""
         _check(lib.clbm_set_resident_limit(self._h, int(max_groups)))
         return self
+
+    @property
+    def step_pairs(self) -> bool:
+        """Whether this lattice advances two fused steps per launch."""
+        return int(lib.clbm_get_step_pairs(self._h)) == 1
+
+    @step_pairs.setter
+    def step_pairs(self, enable: bool):
+        _check(lib.clbm_set_step_pairs(self._h, 1 if enable else 0))
 
     @property
     def occupancy(self) -> int:

@@ -222,6 +222,7 @@ struct clbm_handle {
     int64_t resident_max = clbm::kResidentMaxGroups;  // resident kernel up to this many groups
     size_t lds = 0;              // dynamic LDS per block that enforces occ
     size_t lds0 = 0;             // the same for in-place phase-0 steps
+    bool pairs = true;           // two fused steps per launch where supported
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -240,14 +241,22 @@ void drop_graphs(clbm_handle *h)
 // its own default cap).
 size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0 ? h->lds0 : h->lds; }
 
+// Whether steps go two per launch (the fused two-step kernel).
+bool use_pairs(const clbm_handle *h) { return h->pairs && clbm::step2_supported(h->d); }
+
 int build_graph(clbm_handle *h, int parity)
 {
     hipGraph_t g = nullptr;
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
-    for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
-        le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, step_lds(h, (parity + k) & 1), h->cap);
+    if (use_pairs(h)) {
+        for (int k = 0; k < h->graph_steps / 2 && le == hipSuccess; ++k)
+            le = clbm::launch_step2(h->d, (parity + k) & 1, h->cap);
+    } else {
+        for (int k = 0; k < h->graph_steps && le == hipSuccess; ++k)
+            le = clbm::launch_step(h->d, (parity + k) & 1, h->vec, step_lds(h, (parity + k) & 1), h->cap);
+    }
     hipError_t ce = hipStreamEndCapture(h->cap, &g);
     if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -475,12 +484,20 @@ int clbm_step(clbm_handle *h, int64_t nsteps)
         h->steps += nsteps;
         return CLBM_OK;
     }
+    const bool pairs = use_pairs(h);
     int64_t left = nsteps;
     while (left > 0) {
         if (h->graph_steps > 0 && left >= h->graph_steps) {
             if (!h->graph[h->parity] && (rc = build_graph(h, h->parity))) return rc;
             HIPCHK(hipGraphLaunch(h->graph[h->parity], h->stream));
-            left -= h->graph_steps;  // even, so the parity is unchanged
+            left -= h->graph_steps;
+            // graph_steps is even: one-step launches leave the parity as it
+            // was, fused pairs flip it once per launch.
+            if (pairs) h->parity ^= (h->graph_steps / 2) & 1;
+        } else if (pairs && left >= 2) {
+            HIPCHK(clbm::launch_step2(h->d, h->parity, h->stream));
+            h->parity ^= 1;
+            left -= 2;
         } else {
             HIPCHK(clbm::launch_step(h->d, h->parity, h->vec, step_lds(h, h->parity), h->stream));
             h->parity ^= 1;
@@ -575,6 +592,18 @@ int clbm_set_graph_steps(clbm_handle *h, int32_t steps)
     h->graph_steps = (steps + 1) / 2 * 2;
     return CLBM_OK;
 }
+
+int clbm_set_step_pairs(clbm_handle *h, int32_t enable)
+{
+    g_err.clear();
+    if (!h) return fail(CLBM_EINVAL, "handle is NULL");
+    if (enable != 0 && enable != 1) return fail(CLBM_EINVAL, "enable must be 0 or 1");
+    drop_graphs(h);
+    h->pairs = enable != 0;
+    return CLBM_OK;
+}
+
+int32_t clbm_get_step_pairs(const clbm_handle *h) { return h ? (use_pairs(h) ? 1 : 0) : -1; }
 
 int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu)
 {

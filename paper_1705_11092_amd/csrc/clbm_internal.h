@@ -119,7 +119,13 @@ hipError_t launch_tile_map(const LatDesc *lats, int l_lo, int l_hi, int64_t ntil
 // nsteps steps of a small lattice (no Shan-Chen force) in one launch of one
 // block; vec is the storage type's default nodes per thread.
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s);
+// Two fused steps (temporal blocking) from buffer src into src ^ 1: two
+// buffers, FP32 storage, any force but Shan-Chen (step2_supported).
+bool step2_supported(const LatDesc &d);
+hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s);
 // The same per storage type, one translation unit each (clbm_step_*.hip).
+template <int ST>
+hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s);
 template <int ST>
 hipError_t launch_resident_st(const LatDesc &d, int src, int nsteps, hipStream_t s);
 template <int ST>

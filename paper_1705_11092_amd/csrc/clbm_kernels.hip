@@ -284,6 +284,17 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
     }
 }
 
+bool step2_supported(const LatDesc &d)
+{
+    return !d.inplace && d.storage == ST_F32 && d.force_mode != FM_SC;
+}
+
+hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
+{
+    if (!step2_supported(d)) return hipErrorInvalidValue;
+    return launch_step2_st<ST_F32>(d, src, s);
+}
+
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)
 {
     switch (d.storage) {

@@ -1,0 +1,163 @@
+// clbm_step2.h -- two fused steps per launch (temporal blocking), two-buffer
+// (pull) form.  Included by the translation units of the storage types that
+// use it, after clbm_step.h.
+//
+// One block owns a tile of kTH rows x kTW columns.  Phase A collides step
+// n + 1 on the tile and a one-node halo around it (the nodes whose
+// post-collision values step n + 2 of the tile pulls, Eq. 10), reading the
+// state of step n from HBM, and keeps the results in LDS, rounded to the
+// storage type exactly as the one-step kernel would store them.  Phase B
+// collides step n + 2 on the tile from LDS and writes the other buffer.
+// The state thus crosses HBM once per two steps (plus the halo's re-reads),
+// and every node update is the one-step kernel's, so the result is bitwise
+// that of two one-step launches.
+#pragma once
+
+#include "clbm_step.h"
+
+namespace clbm {
+namespace {
+
+constexpr int kTW = 64, kTH = 16;            // tile: columns x rows (4 nodes per thread in phase B)
+constexpr int kRW = kTW + 2, kRH = kTH + 2;  // the tile with its one-node halo
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+template <int ST, int FM, int SCH>
+__global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
+{
+    static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
+    using S = Storage<ST>;
+    using T = typename S::T;
+    using R = typename S::R;
+    __shared__ T lds[9][kRH][kRW];
+    const T *in = static_cast<const T *>(d.buf[src]);
+    T *out = static_cast<T *>(d.buf[src ^ 1]);
+    // Tiles are numbered row of tiles by row of tiles; xcd_order gives each
+    // XCD a contiguous range, so the halo lines a tile shares with its
+    // neighbours (left, right, above, below) are read once into that L2.
+    const int tiles_x = (d.nx + kTW - 1) / kTW;
+    const int t = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int ty = t / tiles_x;
+    const int x0 = (t - ty * tiles_x) * kTW, y0 = ty * kTH;
+    const Rates<R> rt = rates_of<R>(d);
+
+    // Phase A.  Region node j sits at row y0 - 1 + j / kRW and column
+    // x0 - 1 + j % kRW, both periodic (a lattice narrower or lower than the
+    // region repeats).  Every thread issues the loads of all its region
+    // nodes before colliding any: nodes past the region or beyond a wall
+    // load from a clamped in-lattice place and are not stored (the rows
+    // beyond a wall are never pulled: bounce-back reads the node itself).
+    constexpr int kN = kRW * kRH, kPer = (kN + kBlock - 1) / kBlock;
+    R ga[kPer][9];
+    int rra[kPer], cca[kPer], xa[kPer], ya[kPer];
+    bool keep[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        int j = threadIdx.x + kBlock * m;
+        keep[m] = j < kN;
+        j = j < kN ? j : kN - 1;
+        const int rr = j / kRW, cc = j - rr * kRW;
+        int y = y0 - 1 + rr;
+        if (d.bc_y && (y < 0 || y >= d.ny)) {
+            keep[m] = false;
+            y = y < 0 ? 0 : d.ny - 1;
+        }
+        y = wrap_mod(y, d.ny);
+        const int x = wrap_mod(x0 - 1 + cc, d.nx);
+        rra[m] = rr;
+        cca[m] = cc;
+        xa[m] = x;
+        ya[m] = y;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const Loc s = source_of(d, i, y);
+            const T *rp = in + (int64_t)s.dir * d.dstride + row_base(d, s.row);
+            ga[m][i] = S::to_r(__builtin_nontemporal_load(rp + wrap_x(x - s.dx, d.nx)));
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        R Fx, Fy;
+        force_at<R, FM>(d, xa[m], ya[m], Fx, Fy);
+        collide<R, SCH>(ga[m], Fx, Fy, rt);
+        if (keep[m]) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lds[i][rra[m]][cca[m]] = S::from_r(ga[m][i]);
+        }
+    }
+    __syncthreads();
+
+    // Phase B: 4 consecutive nodes per thread; node (x0 + c + k, y0 + r)
+    // pulls slot i from region row r + 1 - e_y,i and column c + k + 1 - e_x,i,
+    // or, beyond a wall, its own slot opp(i) (region row r + 1, column c + k + 1).
+    const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
+    const int y = y0 + r;
+    if (y >= d.ny || x0 + c >= d.nx) return;
+    R g[4][9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Loc s = source_of(d, i, y);
+        const int rr = s.dir != i ? r + 1 : r + 1 - ey_of(i);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k][i] = S::to_r(lds[s.dir][rr][c + k + 1 - s.dx]);
+    }
+    Pack<T, 4> q[9];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        R Fx, Fy;
+        force_at<R, FM>(d, x0 + c + k < d.nx ? x0 + c + k : d.nx - 1, y, Fx, Fy);
+        collide<R, SCH>(g[k], Fx, Fy, rt);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) q[i].v[k] = S::from_r(g[k][i]);
+    }
+    T *o = out + row_base(d, y) + x0 + c;
+    if (x0 + c + 4 <= d.nx) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) store_pack<T, 4, true>(o + (int64_t)i * d.dstride, q[i]);
+    } else {
+        // The row's last group: real nodes, then copies of the last one in
+        // the padding up to the next multiple of 4, so the row's cache
+        // lines are written whole as the one-step kernel writes them.
+        const int kl = d.nx - 1 - x0 - c;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                if (k > kl) q[i].v[k] = q[i].v[k - 1];
+            store_pack<T, 4, true>(o + (int64_t)i * d.dstride, q[i]);
+        }
+    }
+}
+
+}  // namespace
+
+// Two fused steps of one lattice from buffer src into buffer src ^ 1.
+template <int ST>
+hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)((d.nx + kTW - 1) / kTW) * ((d.ny + kTH - 1) / kTH);
+    const dim3 grid((unsigned)tiles), block(kBlock);
+    switch (d.force_mode * 2 + d.scheme) {
+#define CLBM_S2(FM, SCH)                                          \
+    case FM * 2 + SCH:                                            \
+        k_step2<ST, FM, SCH><<<grid, block, 0, s>>>(d, src);      \
+        break;
+        CLBM_S2(FM_CONST, SCH_CONSISTENT)
+        CLBM_S2(FM_CONST, SCH_GUO_LBL)
+        CLBM_S2(FM_ROW, SCH_CONSISTENT)
+        CLBM_S2(FM_ROW, SCH_GUO_LBL)
+        CLBM_S2(FM_FIELD, SCH_CONSISTENT)
+        CLBM_S2(FM_FIELD, SCH_GUO_LBL)
+#undef CLBM_S2
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace clbm

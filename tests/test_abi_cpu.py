@@ -71,4 +71,6 @@ def test_create_rejects_bad_arguments_before_touching_the_gpu():
     assert clbm.lib.clbm_set_occupancy(None, 3) == clbm.CLBM_EINVAL
     assert clbm.lib.clbm_get_occupancy(None) == -1
     assert clbm.lib.clbm_set_resident_limit(None, 512) == clbm.CLBM_EINVAL
+    assert clbm.lib.clbm_set_step_pairs(None, 1) == clbm.CLBM_EINVAL
+    assert clbm.lib.clbm_get_step_pairs(None) == -1
     assert clbm.lib.clbm_batch_variant_count() >= 1

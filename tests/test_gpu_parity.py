@@ -279,6 +279,45 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
             assert np.max(np.abs(out[0][0] - fo)) <= 1e-12, f"{nx}x{ny} against the oracle"
 
 
+@pytest.mark.parametrize("scheme", ["consistent", "guo_lbl"])
+def test_two_step_kernel_matches_one_step(scheme):
+    # Two fused steps per launch (step n + 1 on a tile and its halo kept in
+    # LDS) give bitwise the one-step kernel's result: every lattice shape of
+    # the parity cases, odd and even step counts, direct launches and graphs.
+    from paper_1705_11092_amd import clbm
+    shapes = CASES + [(130, 40, 1, "const"), (64, 16, 0, "kolmogorov"), (65, 17, 1, "field")]
+    for k, (nx, ny, bc, force) in enumerate(shapes):
+        wl = inputs.random_state(nx, ny, seed=950 + k, bc_y=bc, force=force, amp_f=1e-3,
+                                 amp_u=0.02, s=(1.0, 1.2, 1.25, 1.25, 1.1, 1.1))
+        out = []
+        for pairs, gs in ((False, 0), (True, 0), (True, 6), (True, 64)):
+            lat = gpu_lattice(wl, "f32", scheme)
+            lat.set_resident_limit(0)
+            lat.step_pairs = pairs
+            assert lat.step_pairs == pairs
+            lat.set_graph_steps(gs)
+            lat.step(1)
+            lat.step(20)
+            lat.step(3)
+            rho, ux, uy, tot = lat.moments()
+            out.append((lat.get_populations().cpu().numpy(), rho.cpu().numpy(), ux.cpu().numpy()))
+            lat.close()
+        for o in out[1:]:
+            for a, b in zip(out[0], o):
+                assert np.array_equal(a, b), f"{nx}x{ny} bc={bc} {force} {scheme}"
+    # Lattices the fused kernel does not take step singly and say so.
+    wl = _case(40, 24, 0, "field", 990)
+    for storage, inplace in (("f64", False), ("f16", False), ("f32", True)):
+        lat = gpu_lattice(wl, storage, inplace=inplace)
+        assert not lat.step_pairs
+        lat.close()
+    lat = gpu_lattice(wl, "f32")
+    assert lat.step_pairs
+    with pytest.raises(clbm.ClbmError):
+        clbm._check(clbm.lib.clbm_set_step_pairs(lat.handle, 2))
+    lat.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16sr"])
 def test_occupancy_cap_keeps_results(storage):
     from paper_1705_11092_amd import clbm
