@@ -279,8 +279,8 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
             assert np.max(np.abs(out[0][0] - fo)) <= 1e-12, f"{nx}x{ny} against the oracle"
 
 
-@pytest.mark.parametrize("scheme", ["consistent", "guo_lbl"])
-def test_two_step_kernel_matches_one_step(scheme):
+@pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl")])
+def test_two_step_kernel_matches_one_step(storage, scheme):
     # Two fused steps per launch (step n + 1 on a tile and its halo kept in
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
     # the parity cases, odd and even step counts, direct launches and graphs.
@@ -291,7 +291,7 @@ def test_two_step_kernel_matches_one_step(scheme):
                                  amp_u=0.02, s=(1.0, 1.2, 1.25, 1.25, 1.1, 1.1))
         out = []
         for pairs, gs in ((False, 0), (True, 0), (True, 6), (True, 64)):
-            lat = gpu_lattice(wl, "f32", scheme)
+            lat = gpu_lattice(wl, storage, scheme)
             lat.set_resident_limit(0)
             lat.step_pairs = pairs
             assert lat.step_pairs == pairs
@@ -304,14 +304,14 @@ def test_two_step_kernel_matches_one_step(scheme):
             lat.close()
         for o in out[1:]:
             for a, b in zip(out[0], o):
-                assert np.array_equal(a, b), f"{nx}x{ny} bc={bc} {force} {scheme}"
+                assert np.array_equal(a, b), f"{nx}x{ny} bc={bc} {force} {storage} {scheme}"
     # Lattices the fused kernel does not take step singly and say so.
     wl = _case(40, 24, 0, "field", 990)
-    for storage, inplace in (("f64", False), ("f16", False), ("f32", True)):
-        lat = gpu_lattice(wl, storage, inplace=inplace)
+    for st, inplace in (("f64", False), ("f32", True), ("f16", False), ("bf16sr", False)):
+        lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
-    lat = gpu_lattice(wl, "f32")
+    lat = gpu_lattice(wl, storage)
     assert lat.step_pairs
     with pytest.raises(clbm.ClbmError):
         clbm._check(clbm.lib.clbm_set_step_pairs(lat.handle, 2))
