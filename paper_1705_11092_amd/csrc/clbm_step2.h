@@ -27,6 +27,15 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// v mod n for v in [-1, n + kRW): one add or subtract when the lattice is
+// at least as wide (high) as the region (`big`, the same for every thread),
+// the full remainder otherwise.
+__device__ __forceinline__ int wrap_near(int v, int n, bool big)
+{
+    if (big) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return wrap_mod(v, n);
+}
+
 template <int ST, int FM, int SCH>
 __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
 {
@@ -53,6 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
     // load from a clamped in-lattice place and are not stored (the rows
     // beyond a wall are never pulled: bounce-back reads the node itself).
     constexpr int kN = kRW * kRH, kPer = (kN + kBlock - 1) / kBlock;
+    const bool wide = d.nx >= kRW, high = d.ny >= kRH;
     R ga[kPer][9];
     int rra[kPer], cca[kPer], xa[kPer], ya[kPer];
     bool keep[kPer];
@@ -67,8 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
             keep[m] = false;
             y = y < 0 ? 0 : d.ny - 1;
         }
-        y = wrap_mod(y, d.ny);
-        const int x = wrap_mod(x0 - 1 + cc, d.nx);
+        y = wrap_near(y, d.ny, high);
+        const int x = wrap_near(x0 - 1 + cc, d.nx, wide);
         rra[m] = rr;
         cca[m] = cc;
         xa[m] = x;
