@@ -227,7 +227,7 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     the summary bench.py reports as roofline.traffic."""
     import statistics
     csvs = [os.path.join(d, "run_counter_collection.csv") for d in dirs]
-    step = "k_step2<1, 0, 0>"
+    step = "k_step2<1, 0, 0, unsigned int>"
     fetch = _counter_values(csvs[0], step, "FETCH_SIZE")
     write = _counter_values(csvs[1], step, "WRITE_SIZE")
     cf = statistics.median(_counter_values(csvs[2], "copyBuffer", "FETCH_SIZE"))
@@ -241,7 +241,7 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     step_args = "--steps 6 --warmup 0 --no-cpu-baseline --no-extra"
     copy_args = f"--calibrate-copy {copy_bytes}"
     out = {
-        "kernel": "clbm::k_step2<1, 0, 0> (two fused steps per launch; FP32 deviations, constant "
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int> (two fused steps per launch; FP32 deviations, constant "
                   "force, consistent scheme)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),

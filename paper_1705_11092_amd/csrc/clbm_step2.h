@@ -13,6 +13,8 @@
 // that of two one-step launches.
 #pragma once
 
+#include <type_traits>
+
 #include "clbm_step.h"
 
 namespace clbm {
@@ -36,7 +38,27 @@ __device__ __forceinline__ int wrap_near(int v, int n, bool big)
     return wrap_mod(v, n);
 }
 
-template <int ST, int FM, int SCH>
+// Element e of a buffer.  I = uint32_t (buffers below 4 GB): a 32-bit byte
+// offset from the uniform base, which the loads and stores take as it is
+// (scalar base plus vector offset); I = int64_t otherwise.
+template <typename I, typename T>
+__device__ __forceinline__ T *elem(T *base, I e)
+{
+    if constexpr (sizeof(I) == 4) {
+        using C = std::conditional_t<std::is_const_v<T>, const char, char>;
+        return reinterpret_cast<T *>(reinterpret_cast<C *>(base) + (uint64_t)(uint32_t)(e * (uint32_t)sizeof(T)));
+    } else {
+        return base + e;
+    }
+}
+
+template <typename I>
+__device__ __forceinline__ I row_at(const LatDesc &d, int y)
+{
+    return (I)(y >> d.rshift) * (I)d.bstride + (I)(y & ((1 << d.rshift) - 1)) * (I)d.pitch;
+}
+
+template <int ST, int FM, int SCH, typename I>
 __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
 {
     static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
@@ -83,11 +105,27 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
         cca[m] = cc;
         xa[m] = x;
         ya[m] = y;
+        // The pull sources of node (x, y) lie in rows y - 1, y, y + 1 and
+        // columns x - 1, x, x + 1 (periodic), or, where a row is beyond a
+        // wall, in the node's own reversed slot: the map of source_of,
+        // formed once per node instead of once per direction.
+        const int ym = y - 1, yp = y + 1;
+        const bool in_m = !d.bc_y || ym >= 0, in_p = !d.bc_y || yp < d.ny;
+        const I r0 = row_at<I>(d, y);
+        const I rm = row_at<I>(d, in_m ? (ym < 0 ? ym + d.ny : ym) : y);
+        const I rq = row_at<I>(d, in_p ? (yp >= d.ny ? yp - d.ny : yp) : y);
+        const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const Loc s = source_of(d, i, y);
-            const T *rp = in + (int64_t)s.dir * d.dstride + row_base(d, s.row);
-            ga[m][i] = S::to_r(__builtin_nontemporal_load(rp + wrap_x(x - s.dx, d.nx)));
+            const int xs = ex_of(i) == 1 ? xm : (ex_of(i) == -1 ? xp : x);
+            I e;
+            if (ey_of(i) == 0)
+                e = r0 + (I)i * (I)d.dstride + (I)xs;
+            else if (ey_of(i) == 1)
+                e = in_m ? rm + (I)i * (I)d.dstride + (I)xs : r0 + (I)opp_of(i) * (I)d.dstride + (I)x;
+            else
+                e = in_p ? rq + (I)i * (I)d.dstride + (I)xs : r0 + (I)opp_of(i) * (I)d.dstride + (I)x;
+            ga[m][i] = S::to_r(__builtin_nontemporal_load(elem<I>(in, e)));
         }
     }
 #pragma unroll
@@ -108,13 +146,17 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
     const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
     const int y = y0 + r;
     if (y >= d.ny || x0 + c >= d.nx) return;
+    // Beyond a wall (row y - 1 or y + 1 outside the lattice) the node reads
+    // its own slot opp(i); otherwise region row r + 1 - e_y,i.
+    const bool in_m = !d.bc_y || y >= 1, in_p = !d.bc_y || y + 1 < d.ny;
     R g[4][9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const Loc s = source_of(d, i, y);
-        const int rr = s.dir != i ? r + 1 : r + 1 - ey_of(i);
+        const T *a = &lds[i][r + 1 - ey_of(i)][c + 1 - ex_of(i)];
+        if (ey_of(i) == 1 && !in_m) a = &lds[opp_of(i)][r + 1][c + 1];
+        if (ey_of(i) == -1 && !in_p) a = &lds[opp_of(i)][r + 1][c + 1];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g[k][i] = S::to_r(lds[s.dir][rr][c + k + 1 - s.dx]);
+        for (int k = 0; k < 4; ++k) g[k][i] = S::to_r(a[k]);
     }
     Pack<T, 4> q[9];
 #pragma unroll
@@ -125,10 +167,10 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
 #pragma unroll
         for (int i = 0; i < 9; ++i) q[i].v[k] = S::from_r(g[k][i]);
     }
-    T *o = out + row_base(d, y) + x0 + c;
+    const I ob = row_at<I>(d, y) + (I)(x0 + c);
     if (x0 + c + 4 <= d.nx) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) store_pack<T, 4, true>(o + (int64_t)i * d.dstride, q[i]);
+        for (int i = 0; i < 9; ++i) store_pack<T, 4, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
     } else {
         // The row's last group: real nodes, then copies of the last one in
         // the padding up to the next multiple of 4, so the row's cache
@@ -139,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
 #pragma unroll
             for (int k = 1; k < 4; ++k)
                 if (k > kl) q[i].v[k] = q[i].v[k - 1];
-            store_pack<T, 4, true>(o + (int64_t)i * d.dstride, q[i]);
+            store_pack<T, 4, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
         }
     }
 }
@@ -152,10 +194,17 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
 {
     const int64_t tiles = (int64_t)((d.nx + kTW - 1) / kTW) * ((d.ny + kTH - 1) / kTH);
     const dim3 grid((unsigned)tiles), block(kBlock);
+    // Elements of one buffer: whole row blocks of bstride elements.
+    const int64_t rows = (int64_t)1 << d.rshift;
+    const int64_t elems = (d.ny + rows - 1) / rows * d.bstride;
+    const bool small = elems * (int64_t)sizeof(typename Storage<ST>::T) + 4096 < ((int64_t)1 << 32);
     switch (d.force_mode * 2 + d.scheme) {
-#define CLBM_S2(FM, SCH)                                          \
-    case FM * 2 + SCH:                                            \
-        k_step2<ST, FM, SCH><<<grid, block, 0, s>>>(d, src);      \
+#define CLBM_S2(FM, SCH)                                                          \
+    case FM * 2 + SCH:                                                            \
+        if (small)                                                                \
+            k_step2<ST, FM, SCH, uint32_t><<<grid, block, 0, s>>>(d, src);        \
+        else                                                                      \
+            k_step2<ST, FM, SCH, int64_t><<<grid, block, 0, s>>>(d, src);         \
         break;
         CLBM_S2(FM_CONST, SCH_CONSISTENT)
         CLBM_S2(FM_CONST, SCH_GUO_LBL)

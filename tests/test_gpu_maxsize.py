@@ -56,3 +56,31 @@ def test_largest_square_lattice_fp16():
     # Momentum grows by the summed force each step: zero for a whole number
     # of sine periods; mass stays.
     assert abs(tot[0] - float(N) * N) <= 1e-6 * N * N
+
+
+def test_two_step_kernel_above_4gb_fp32():
+    # An FP32 lattice whose buffers exceed 4 GB (11000^2: 4.36 GB each) takes
+    # the two-step kernel's 64-bit addressing; its result must equal single
+    # steps bitwise (fields compared on the device).
+    import torch
+    from paper_1705_11092_amd import clbm
+    n = 11000
+    assert clbm.buffer_bytes(n, n, "f32") > 2**32
+    rates = (1.0, 1.0, 1.25, 1.25, 1.0, 1.0)
+    out = []
+    for pairs in (False, True):
+        lat = clbm.Lattice(n, n, rates, storage="f32", bc_y="bounceback")
+        lat.set_force("kolmogorov", params=(1e-4, 2))
+        lat.init()
+        lat.step_pairs = pairs
+        assert lat.step_pairs == pairs
+        lat.step(5)
+        rho, ux, uy, tot = lat.moments()
+        out.append((rho, ux, uy))
+        lat.close()
+        del lat
+    log(f"{n}^2 f32, 5 steps: pairs vs single steps compared on the device")
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    del out
+    torch.cuda.empty_cache()
