@@ -146,13 +146,15 @@ def run_small():
 
 def run_batch(steps: int, warmup: int, count: int = 256):
     """The batch of uneven Kolmogorov lattices (sides log-uniform in
-    [32, 512], seed 0), FP32 storage, one persistent launch per step."""
+    [32, 512], seed 0), FP32 storage, two fused steps per launch over all
+    lattices (hbm_frac: 72 B per node per launch, i.e. per two updates)."""
     import torch
     from paper_1705_11092_amd import clbm, inputs
 
     wls = inputs.kolmogorov_batch(count=count, seed=0, steps=steps)
     lats = [clbm.lattice_from_workload(wl, storage="f32") for wl in wls]
     b = clbm.Batch(lats)
+    per_launch = 2 if lats[0].step_pairs else 1
     variant = b.autotune(None)
     b.step(warmup)
     torch.cuda.synchronize()
@@ -170,7 +172,8 @@ def run_batch(steps: int, warmup: int, count: int = 256):
     mlups = nodes * steps / (ms / 1e3) / 1e6
     return {"workload": f"{count} Kolmogorov lattices, sides log-uniform 32..512 (seed 0), f32",
             "nodes": nodes, "steps": steps, "ms_per_step": round(ms / steps, 5),
-            "mlups": round(mlups, 1), "hbm_frac": round(mlups * 1e6 * 72 / 8e12, 4),
+            "mlups": round(mlups, 1), "steps_per_launch": per_launch,
+            "hbm_frac": round(mlups * 1e6 * 72 / per_launch / 8e12, 4),
             "variant": variant}
 
 

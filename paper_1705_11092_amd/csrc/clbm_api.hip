@@ -685,6 +685,8 @@ struct clbm_batch {
         int64_t ntiles;
         int64_t tbase;                // first entry of the group in the tile map
         size_t lds;                   // dynamic LDS per block enforcing the cap
+        bool pairs;                   // two fused steps per launch (64 x 16 tiles)
+        bool small;                   // pairs: every buffer below 4 GB
     };
     std::vector<Group> groups;
     std::vector<LatDesc> tab;         // host copy of the table's geometry
@@ -699,9 +701,12 @@ struct clbm_batch {
 
 namespace {
 
-// Launch group of a lattice: storage type and kernel (storage scheme, force
-// mode, forcing scheme).
-int group_key(const LatDesc &d) { return d.storage * clbm::kKernelKeys + clbm::kernel_key(d); }
+// Launch group of a lattice: whether it steps in pairs, storage type and
+// kernel (storage scheme, force mode, forcing scheme).
+int group_key(const clbm_handle *h)
+{
+    return ((use_pairs(h) ? 1 : 0) * kStorageKinds + h->d.storage) * clbm::kKernelKeys + clbm::kernel_key(h->d);
+}
 
 // Table order: grouped by storage and kernel (one launch per group), caller
 // order inside a group.
@@ -709,10 +714,10 @@ void batch_order(clbm_batch *b)
 {
     b->order.clear();
     b->keys.clear();
-    for (int key = 0; key < kStorageKinds * clbm::kKernelKeys; ++key)
+    for (int key = 0; key < 2 * kStorageKinds * clbm::kKernelKeys; ++key)
         for (size_t j = 0; j < b->lats.size(); ++j)
-            if (group_key(b->lats[j]->d) == key) b->order.push_back((int)j);
-    for (auto *h : b->lats) b->keys.push_back(group_key(h->d));
+            if (group_key(b->lats[j]) == key) b->order.push_back((int)j);
+    for (auto *h : b->lats) b->keys.push_back(group_key(h));
 }
 
 // Geometry of the current variant: per lattice nodes per thread, tile
@@ -724,26 +729,34 @@ void batch_geometry(clbm_batch *b)
     b->tab.assign(b->order.size(), LatDesc());
     size_t pos = 0;
     while (pos < b->order.size()) {
-        const LatDesc &d0 = b->lats[b->order[pos]]->d;
-        const int key = group_key(d0);
+        const clbm_handle *h0 = b->lats[b->order[pos]];
+        const LatDesc &d0 = h0->d;
+        const int key = group_key(h0);
+        const bool pairs = use_pairs(h0);
         const int st = d0.storage;
-        const int vec = vec_for(st, kVariants[b->variant].vec_bytes);
+        const int vec = pairs ? 4 : vec_for(st, kVariants[b->variant].vec_bytes);
         const int lo = (int)pos;
         int64_t tiles = 0;
-        size_t bytes = 0;
-        while (pos < b->order.size() && group_key(b->lats[b->order[pos]]->d) == key) {
+        size_t bytes = 0, largest = 0;
+        while (pos < b->order.size() && group_key(b->lats[b->order[pos]]) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
             clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
+            if (pairs)  // tiles of the two-step kernel: 64 columns x 16 rows
+                d.ntiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + 15) / 16);
             d.vec = vec;
+            d.pairs = pairs ? 1 : 0;
             d.tile0 = tiles;
             tiles += d.ntiles;
-            bytes += 2 * clbm_buffer_bytes(d.nx, d.ny, d.storage);
+            const size_t one = clbm_buffer_bytes(d.nx, d.ny, d.storage);
+            bytes += 2 * one;
+            largest = std::max(largest, one);
             b->tab[pos] = d;
             ++pos;
         }
         const int cap = kVariants[b->variant].cap;
         const size_t lds = lds_for_occupancy(cap < 0 ? default_occupancy(st, bytes) : cap);
-        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds});
+        const bool small = largest + 4096 < ((size_t)1 << 32);
+        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds, pairs, small});
         tbase += tiles;
     }
     b->map_dirty = true;
@@ -771,6 +784,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
             d.vec = g.vec;
             d.tile0 = g.tile0;
             d.ntiles = g.ntiles;
+            d.pairs = g.pairs;
             d.parity = h->parity;
             d.steps = (int32_t)nsteps[b->order[pos]];
             if (scratch && d.inplace) d.buf[1] = scratch;
@@ -804,7 +818,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
 void batch_refresh(clbm_batch *b)
 {
     for (size_t j = 0; j < b->lats.size(); ++j) {
-        if (group_key(b->lats[j]->d) != b->keys[j]) {
+        if (group_key(b->lats[j]) != b->keys[j]) {
             batch_order(b);
             batch_geometry(b);
             return;
@@ -846,10 +860,17 @@ int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s)
     }
     for (size_t k = 0; k < ng; ++k) {
         const auto &g = b->groups[k];
+        hipStream_t gs = k == 0 ? s : b->side[k - 1];
+        if (g.pairs) {
+            // Steps k0 .. k0 + n - 1 as pair substeps (k0 is even).
+            for (int p = k0 / 2; p < (k0 + n + 1) / 2; ++p)
+                HIPCHK(clbm::launch_batch2(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key, g.small, p, gs));
+            continue;
+        }
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
         for (int sub = k0; sub < k0 + n; ++sub)
             HIPCHK(clbm::launch_batch(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.storage, g.key,
-                                      g.vec, gg, sub, g.lds, k == 0 ? s : b->side[k - 1]));
+                                      g.vec, gg, sub, g.lds, gs));
     }
     for (size_t k = 1; k < ng; ++k) {
         HIPCHK(hipEventRecord(b->join[k - 1], b->side[k - 1]));
@@ -907,7 +928,10 @@ int batch_run(clbm_batch *b, const int64_t *nsteps)
         HIPCHK(clbm::launch_batch_advance(b->d_lats, (int)b->order.size(), (int)left, b->stream));
     }
     for (size_t j = 0; j < b->lats.size(); ++j) {
-        b->lats[j]->parity = (int)((b->lats[j]->parity + nsteps[j]) & 1);
+        // Lattices stepping in pairs flip buffers once per launch; every
+        // chunk but a lattice's last holds an even number of its steps.
+        const int64_t launches = use_pairs(b->lats[j]) ? (nsteps[j] + 1) / 2 : nsteps[j];
+        b->lats[j]->parity = (int)((b->lats[j]->parity + launches) & 1);
         b->lats[j]->steps += nsteps[j];
     }
     return CLBM_OK;

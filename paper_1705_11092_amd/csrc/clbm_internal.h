@@ -64,6 +64,7 @@ struct LatDesc {
     int32_t vec;         // nodes per thread along x
     int32_t inplace;     // 0: two buffers (pull form); 1: one buffer, AA pattern
     int32_t rshift;      // log2 of the rows per row block
+    int32_t pairs;       // batch: steps go two per launch (64 x 16 tiles, parity counts launches)
     int64_t tile0;       // batch: first tile of this lattice in its group
     int64_t ntiles;      // batch: tiles of this lattice
     double inv_tpr;      // 1 / tpr, for the tile decode
@@ -123,7 +124,16 @@ hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)
 // buffers, FP32 storage, any force but Shan-Chen (step2_supported).
 bool step2_supported(const LatDesc &d);
 hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s);
+// Pair substep `pair` of a batch group whose lattices step in pairs: each
+// lattice with at least 2 pair + 2 steps left takes two fused steps, one
+// with 2 pair + 1 left takes its last single step.  small: every buffer of
+// the group is below 4 GB.
+hipError_t launch_batch2(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
+                         bool small, int pair, hipStream_t s);
 // The same per storage type, one translation unit each (clbm_step_*.hip).
+template <int ST>
+hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
+                            bool small, int pair, hipStream_t s);
 template <int ST>
 hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s);
 template <int ST>

@@ -47,7 +47,10 @@ __global__ void k_batch_advance(LatDesc *lats, int count, int chunk)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < count) {
         const int done = lats[j].steps < chunk ? lats[j].steps : chunk;
-        lats[j].parity = (lats[j].parity + done) & 1;
+        // Lattices stepping in pairs flip buffers once per launch: done / 2
+        // pairs and, for an odd count, one single step.
+        const int launches = lats[j].pairs ? (done + 1) / 2 : done;
+        lats[j].parity = (lats[j].parity + launches) & 1;
         lats[j].steps -= done;
     }
 }
@@ -293,6 +296,12 @@ hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
 {
     if (!step2_supported(d)) return hipErrorInvalidValue;
     return launch_step2_st<ST_F32>(d, src, s);
+}
+
+hipError_t launch_batch2(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
+                         int pair, hipStream_t s)
+{
+    return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
 }
 
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)

@@ -58,23 +58,16 @@ __device__ __forceinline__ I row_at(const LatDesc &d, int y)
     return (I)(y >> d.rshift) * (I)d.bstride + (I)(y & ((1 << d.rshift) - 1)) * (I)d.pitch;
 }
 
+// Two fused steps of the tile at (x0, y0) from buffer src into src ^ 1.
 template <int ST, int FM, int SCH, typename I>
-__global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
+__device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int y0,
+                                          typename Storage<ST>::T (&lds)[9][kRH][kRW])
 {
-    static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
     using S = Storage<ST>;
     using T = typename S::T;
     using R = typename S::R;
-    __shared__ T lds[9][kRH][kRW];
     const T *in = static_cast<const T *>(d.buf[src]);
     T *out = static_cast<T *>(d.buf[src ^ 1]);
-    // Tiles are numbered row of tiles by row of tiles; xcd_order gives each
-    // XCD a contiguous range, so the halo lines a tile shares with its
-    // neighbours (left, right, above, below) are read once into that L2.
-    const int tiles_x = (d.nx + kTW - 1) / kTW;
-    const int t = (int)xcd_order(blockIdx.x, gridDim.x);
-    const int ty = t / tiles_x;
-    const int x0 = (t - ty * tiles_x) * kTW, y0 = ty * kTH;
     const Rates<R> rt = rates_of<R>(d);
 
     // Phase A.  Region node j sits at row y0 - 1 + j / kRW and column
@@ -186,6 +179,50 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
     }
 }
 
+
+template <int ST, int FM, int SCH, typename I>
+__global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src)
+{
+    static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
+    __shared__ typename Storage<ST>::T lds[9][kRH][kRW];
+    // Tiles are numbered row of tiles by row of tiles; xcd_order gives each
+    // XCD a contiguous range, so the halo lines a tile shares with its
+    // neighbours (left, right, above, below) are read once into that L2.
+    const int tiles_x = (d.nx + kTW - 1) / kTW;
+    const int t = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int ty = t / tiles_x;
+    pair_tile<ST, FM, SCH, I>(d, src, (t - ty * tiles_x) * kTW, ty * kTH, lds);
+}
+
+// Pair substep `pair` of a batch group (tiles numbered lattice by lattice,
+// tile_lat naming each tile's lattice).  A lattice with at least two steps
+// left in this sequence takes two fused steps; one with one step left takes
+// it with the one-step node update (the group's step count may be odd).
+// The buffer parity of these lattices counts launches: pair p reads buffer
+// parity + p.
+template <int ST, int FM, int SCH, typename I>
+__global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ lats,
+                                                   const int32_t *__restrict__ tile_lat, int64_t ntiles,
+                                                   int pair)
+{
+    __shared__ typename Storage<ST>::T lds[9][kRH][kRW];
+    const int64_t t = xcd_order(blockIdx.x, ntiles);
+    const LatDesc &d = lats[tile_lat[t]];
+    const int left = d.steps - 2 * pair;
+    if (left <= 0) return;  // the whole block: one lattice per tile
+    const int64_t lt = t - d.tile0;
+    const int tiles_x = (d.nx + kTW - 1) / kTW;
+    const int ty = (int)(lt / tiles_x);
+    const int x0 = (int)(lt - (int64_t)ty * tiles_x) * kTW, y0 = ty * kTH;
+    const int src = (d.parity + pair) & 1;
+    if (left >= 2) {
+        pair_tile<ST, FM, SCH, I>(d, src, x0, y0, lds);
+    } else {
+        const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
+        if (y0 + r < d.ny && x0 + c < d.nx) step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
+    }
+}
+
 }  // namespace
 
 // Two fused steps of one lattice from buffer src into buffer src ^ 1.
@@ -213,6 +250,32 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
         CLBM_S2(FM_FIELD, SCH_CONSISTENT)
         CLBM_S2(FM_FIELD, SCH_GUO_LBL)
 #undef CLBM_S2
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
+                            int pair, hipStream_t s)
+{
+    const dim3 grid((unsigned)ntiles), block(kBlock);
+    switch (key) {
+#define CLBM_B2(FM, SCH)                                                                      \
+    case FM * 2 + SCH:                                                                        \
+        if (small)                                                                            \
+            k_batch2<ST, FM, SCH, uint32_t><<<grid, block, 0, s>>>(lats, tile_lat, ntiles, pair); \
+        else                                                                                  \
+            k_batch2<ST, FM, SCH, int64_t><<<grid, block, 0, s>>>(lats, tile_lat, ntiles, pair);  \
+        break;
+        CLBM_B2(FM_CONST, SCH_CONSISTENT)
+        CLBM_B2(FM_CONST, SCH_GUO_LBL)
+        CLBM_B2(FM_ROW, SCH_CONSISTENT)
+        CLBM_B2(FM_ROW, SCH_GUO_LBL)
+        CLBM_B2(FM_FIELD, SCH_CONSISTENT)
+        CLBM_B2(FM_FIELD, SCH_GUO_LBL)
+#undef CLBM_B2
     default:
         return hipErrorInvalidValue;
     }

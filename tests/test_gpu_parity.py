@@ -159,6 +159,39 @@ def test_batch_is_bitwise_equal_to_single():
             lat.close()
 
 
+def test_batch_pairs_equal_single_steps():
+    # Two-buffer FP32 lattices in a batch advance two fused steps per launch;
+    # per-lattice step counts may be odd (the last step alone) or span several
+    # graph chunks.  Results equal the batch stepping singly, bitwise, for
+    # every lattice; in-place and 16-bit lattices step singly either way.
+    from paper_1705_11092_amd import clbm
+    shapes = [(37, 23, 0, "field", "f32", False), (300, 70, 1, "field", "f32", False),
+              (64, 32, 1, "const", "f32", False), (130, 40, 0, "kolmogorov", "f32", False),
+              (1, 17, 1, "const", "f32", False), (96, 20, 1, "none", "f32", True),
+              (80, 48, 0, "field", "f16", False)]
+    counts = [70, 33, 5, 1, 0, 9, 12]
+    out = []
+    for pairs in (False, True):
+        lats = []
+        for k, (nx, ny, bc, force, storage, inplace) in enumerate(shapes):
+            wl = inputs.random_state(nx, ny, seed=970 + k, bc_y=bc, force=force, amp_f=1e-3,
+                                     amp_u=0.02, s=(1.0, 1.2, 1.25, 1.25, 1.1, 1.1))
+            lat = gpu_lattice(wl, storage, inplace=inplace)
+            lat.step_pairs = pairs
+            lats.append(lat)
+        b = clbm.Batch(lats)
+        b.step_each(counts)
+        b.step_each([3, 2, 1, 4, 7, 0, 5])
+        b.step(40)
+        out.append([lat.get_populations().cpu().numpy() for lat in lats])
+        assert [lat.steps for lat in lats] == [c1 + c2 + 40 for c1, c2 in zip(counts, [3, 2, 1, 4, 7, 0, 5])]
+        b.close()
+        for lat in lats:
+            lat.close()
+    for k, (a, c) in enumerate(zip(out[0], out[1])):
+        assert np.array_equal(a, c), f"lattice {k} {shapes[k]}"
+
+
 def test_batch_follows_a_force_change():
     # A lattice switching force mode between batch calls moves to another
     # kernel; its result must equal a solo run with the same force history.
