@@ -318,7 +318,8 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
     # the parity cases, odd and even step counts, direct launches and graphs.
     from paper_1705_11092_amd import clbm
-    shapes = CASES + [(130, 40, 1, "const"), (64, 16, 0, "kolmogorov"), (65, 17, 1, "field")]
+    shapes = CASES + [(130, 40, 1, "const"), (64, 16, 0, "kolmogorov"), (65, 17, 1, "field"),
+              (33, 1, 1, "field"), (70, 2, 1, "kolmogorov"), (129, 33, 1, "none")]
     for k, (nx, ny, bc, force) in enumerate(shapes):
         wl = inputs.random_state(nx, ny, seed=950 + k, bc_y=bc, force=force, amp_f=1e-3,
                                  amp_u=0.02, s=(1.0, 1.2, 1.25, 1.25, 1.1, 1.1))
