@@ -37,14 +37,26 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-// v mod n for v in [-1, n + kRW): one add or subtract when the lattice is
-// at least as wide (high) as the region (`big`, the same for every thread),
-// the full remainder otherwise.
-__device__ __forceinline__ int wrap_near(int v, int n, bool big)
-{
-    if (big) return v < 0 ? v + n : (v >= n ? v - n : v);
-    return wrap_mod(v, n);
-}
+// Per-block tables of the region's coordinates, filled once per tile so
+// that each region node reads its source offsets instead of forming them.
+// Offsets are in address units: bytes for 32-bit offsets (I = uint32_t),
+// elements otherwise.
+template <typename I>
+struct alignas(16) RowEnt {
+    I r0, rm, rq;  // the region row's own row, and the rows its slots with
+                   // e_y = +1 and -1 pull from (its own row beyond a wall)
+    int32_t y;     // lattice row, or -1 for a row beyond a wall
+};
+template <typename I>
+struct alignas(16) ColEnt {
+    I om, o0, op;  // columns x - 1, x, x + 1 (periodic)
+    int32_t x;
+};
+template <typename I>
+struct TileTabs {
+    RowEnt<I> row[kRH];
+    ColEnt<I> col[kRW];
+};
 
 // Element e of a buffer.  I = uint32_t (buffers below 4 GB): a 32-bit byte
 // offset from the uniform base, which the loads and stores take as it is
@@ -60,6 +72,18 @@ __device__ __forceinline__ T *elem(T *base, I e)
     }
 }
 
+// Address `off` address units past base (see TileTabs).
+template <typename I, typename T>
+__device__ __forceinline__ T *at(T *base, I off)
+{
+    if constexpr (sizeof(I) == 4) {
+        using C = std::conditional_t<std::is_const_v<T>, const char, char>;
+        return reinterpret_cast<T *>(reinterpret_cast<C *>(base) + (uint64_t)off);
+    } else {
+        return base + off;
+    }
+}
+
 template <typename I>
 __device__ __forceinline__ I row_at(const LatDesc &d, int y)
 {
@@ -69,7 +93,7 @@ __device__ __forceinline__ I row_at(const LatDesc &d, int y)
 // Two fused steps of the tile at (x0, y0) from buffer src into src ^ 1.
 template <int ST, int FM, int SCH, typename I>
 __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int y0,
-                                          typename Storage<ST>::T (&lds)[9][kTH][kTW])
+                                          typename Storage<ST>::T (&lds)[9][kTH][kTW], TileTabs<I> &tab)
 {
     using S = Storage<ST>;
     using T = typename S::T;
@@ -78,60 +102,87 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     T *out = static_cast<T *>(d.buf[src ^ 1]);
     const Rates<R> rt = rates_of<R>(d);
 
-    // Phase A.  Region node j sits at row y0 - 1 + j / kRW and column
-    // x0 - 1 + j % kRW, both periodic (a lattice narrower or lower than the
-    // region repeats).  Every thread issues the loads of all its region
-    // nodes before colliding any: nodes past the region or beyond a wall
-    // load from a clamped in-lattice place and are not stored (the rows
-    // beyond a wall are never pulled: bounce-back reads the node itself).
+    // Phase A: step n + 1 on the region, the tile and its one-node halo.
     // The loads are ordinary, not non-temporal: the halo's lines are the
     // neighbouring tiles' own, read again a few tiles later, and the L2
     // keeps them only if they were not fetched with the streaming policy
     // (with non-temporal loads the fetched bytes were 1.31 times the state
     // read, with ordinary loads 1.04 times).
     constexpr int kN = kRW * kRH, kPer = (kN + kBlock - 1) / kBlock;
-    const bool wide = d.nx >= kRW, high = d.ny >= kRH;
+    constexpr I kU = sizeof(I) == 4 ? (I)sizeof(T) : (I)1;  // address units per element
+    // The tables: region row rr is lattice row y0 - 1 + rr, region column cc
+    // lattice column x0 - 1 + cc, both periodic (a lattice narrower or lower
+    // than the region repeats); a row beyond a wall is marked and takes the
+    // wall row's offsets.  The pull sources of node (x, y) lie in rows
+    // y - 1, y, y + 1 and columns x - 1, x, x + 1, or, where a row is beyond
+    // a wall, in the node's own reversed slot.
+    if (threadIdx.x < kRH) {
+        const int rr = threadIdx.x;
+        int y = y0 - 1 + rr;
+        bool beyond = false;
+        if (d.bc_y && (y < 0 || y >= d.ny)) {
+            beyond = true;
+            y = y < 0 ? 0 : d.ny - 1;
+        }
+        y = wrap_mod(y, d.ny);
+        const int ym = y - 1, yp = y + 1;
+        const bool in_m = !d.bc_y || ym >= 0, in_p = !d.bc_y || yp < d.ny;
+        RowEnt<I> e;
+        e.r0 = row_at<I>(d, y) * kU;
+        e.rm = row_at<I>(d, in_m ? (ym < 0 ? ym + d.ny : ym) : y) * kU;
+        e.rq = row_at<I>(d, in_p ? (yp >= d.ny ? yp - d.ny : yp) : y) * kU;
+        e.y = beyond ? -1 : y;
+        tab.row[rr] = e;
+    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kRW) {
+        const int cc = threadIdx.x - 64;
+        const int x = wrap_mod(x0 - 1 + cc, d.nx);
+        ColEnt<I> e;
+        e.om = (I)(x == 0 ? d.nx - 1 : x - 1) * kU;
+        e.o0 = (I)x * kU;
+        e.op = (I)(x == d.nx - 1 ? 0 : x + 1) * kU;
+        e.x = x;
+        tab.col[cc] = e;
+    }
+    __syncthreads();
+    // Slot i's plane, in address units.
+    I so[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) so[i] = (I)i * (I)d.dstride * kU;
+
+    // Region node j is region row j / kRW, column j % kRW.  Every thread
+    // issues the loads of all its region nodes before colliding any: nodes
+    // past the region or beyond a wall load from an in-lattice place and
+    // are not stored (the rows beyond a wall are never pulled: bounce-back
+    // reads the node itself).
     R ga[kPer][9];
     int rra[kPer], cca[kPer], xa[kPer], ya[kPer];
     bool keep[kPer];
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
         int j = threadIdx.x + kBlock * m;
-        keep[m] = j < kN;
-        j = j < kN ? j : kN - 1;
+        const bool inr = j < kN;
+        j = inr ? j : kN - 1;
         const int rr = j / kRW, cc = j - rr * kRW;
-        int y = y0 - 1 + rr;
-        if (d.bc_y && (y < 0 || y >= d.ny)) {
-            keep[m] = false;
-            y = y < 0 ? 0 : d.ny - 1;
-        }
-        y = wrap_near(y, d.ny, high);
-        const int x = wrap_near(x0 - 1 + cc, d.nx, wide);
+        const RowEnt<I> re = tab.row[rr];
+        const ColEnt<I> ce = tab.col[cc];
+        keep[m] = inr && re.y >= 0;
+        const int y = re.y < 0 ? 0 : re.y;
         rra[m] = rr;
         cca[m] = cc;
-        xa[m] = x;
+        xa[m] = ce.x;
         ya[m] = y;
-        // The pull sources of node (x, y) lie in rows y - 1, y, y + 1 and
-        // columns x - 1, x, x + 1 (periodic), or, where a row is beyond a
-        // wall, in the node's own reversed slot: the map of source_of,
-        // formed once per node instead of once per direction.
-        const int ym = y - 1, yp = y + 1;
-        const bool in_m = !d.bc_y || ym >= 0, in_p = !d.bc_y || yp < d.ny;
-        const I r0 = row_at<I>(d, y);
-        const I rm = row_at<I>(d, in_m ? (ym < 0 ? ym + d.ny : ym) : y);
-        const I rq = row_at<I>(d, in_p ? (yp >= d.ny ? yp - d.ny : yp) : y);
-        const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+        const bool in_m = !d.bc_y || y >= 1, in_p = !d.bc_y || y + 1 < d.ny;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const int xs = ex_of(i) == 1 ? xm : (ex_of(i) == -1 ? xp : x);
+            const I xs = ex_of(i) == 1 ? ce.om : (ex_of(i) == -1 ? ce.op : ce.o0);
             I e;
             if (ey_of(i) == 0)
-                e = r0 + (I)i * (I)d.dstride + (I)xs;
+                e = re.r0 + so[i] + xs;
             else if (ey_of(i) == 1)
-                e = in_m ? rm + (I)i * (I)d.dstride + (I)xs : r0 + (I)opp_of(i) * (I)d.dstride + (I)x;
+                e = in_m ? re.rm + so[i] + xs : re.r0 + so[opp_of(i)] + ce.o0;
             else
-                e = in_p ? rq + (I)i * (I)d.dstride + (I)xs : r0 + (I)opp_of(i) * (I)d.dstride + (I)x;
-            ga[m][i] = S::to_r(*elem<I>(in, e));
+                e = in_p ? re.rq + so[i] + xs : re.r0 + so[opp_of(i)] + ce.o0;
+            ga[m][i] = S::to_r(*at<I>(in, e));
         }
     }
 #pragma unroll
@@ -228,6 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
 {
     static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
     __shared__ __align__(16) typename Storage<ST>::T lds[9][kTH][kTW];
+    __shared__ TileTabs<I> tab;
     // xcd_order gives each XCD a contiguous range of tile numbers, and the
     // strip walk puts a tile's left neighbour one tile and the one above it
     // sw tiles earlier in that range, so the halo lines a tile shares with
@@ -236,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
     const int t = (int)xcd_order(blockIdx.x, gridDim.x);
     int tx, ty;
     strip_tile(t, tiles_x, tiles_y, sw, tx, ty);
-    pair_tile<ST, FM, SCH, I>(d, src, tx * kTW, ty * kTH, lds);
+    pair_tile<ST, FM, SCH, I>(d, src, tx * kTW, ty * kTH, lds, tab);
 }
 
 // Pair substep `pair` of a batch group (tiles numbered lattice by lattice,
@@ -251,6 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ l
                                                    int pair)
 {
     __shared__ __align__(16) typename Storage<ST>::T lds[9][kTH][kTW];
+    __shared__ TileTabs<I> tab;
     const int64_t t = xcd_order(blockIdx.x, ntiles);
     const LatDesc &d = lats[tile_lat[t]];
     const int left = d.steps - 2 * pair;
@@ -261,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ l
     const int x0 = (int)(lt - (int64_t)ty * tiles_x) * kTW, y0 = ty * kTH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
-        pair_tile<ST, FM, SCH, I>(d, src, x0, y0, lds);
+        pair_tile<ST, FM, SCH, I>(d, src, x0, y0, lds, tab);
     } else {
         const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
         if (y0 + r < d.ny && x0 + c < d.nx) step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
