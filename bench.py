@@ -370,9 +370,17 @@ def main():
             "footprint_bytes": nodes * bpl // 2}
         for st in ("f64", "f16", "bf16", "f16sr", "bf16sr"):
             ms16, _, _ = run_gpu(args.n, st, args.steps, args.warmup)
+            spl = 2 if run_gpu.pairs else 1
             m = nodes / (ms16 / args.steps / 1e3) / 1e6
             extra[st] = {"mlups": round(m, 1), "ms_per_step": round(ms16 / args.steps, 5),
-                         "hbm_frac": round(m * 1e6 * BYTES_PER_LUP[st] / 8e12, 4)}
+                         "steps_per_launch": spl,
+                         "hbm_frac": round(m * 1e6 * BYTES_PER_LUP[st] / spl / 8e12, 4)}
+            if spl == 2:
+                ms1, _, _ = run_gpu(args.n, st, args.steps, args.warmup, pairs=False)
+                m1 = nodes / (ms1 / args.steps / 1e3) / 1e6
+                extra[f"{st}_one_step_per_launch"] = {
+                    "mlups": round(m1, 1), "ms_per_step": round(ms1 / args.steps, 5),
+                    "hbm_frac": round(m1 * 1e6 * BYTES_PER_LUP[st] / 8e12, 4)}
         extra["batch"] = run_batch(1000, 20)
         extra.update(run_small())
         if args.serve_requests > 0:

@@ -864,7 +864,7 @@ int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s)
         if (g.pairs) {
             // Steps k0 .. k0 + n - 1 as pair substeps (k0 is even).
             for (int p = k0 / 2; p < (k0 + n + 1) / 2; ++p)
-                HIPCHK(clbm::launch_batch2(b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key, g.small, p, gs));
+                HIPCHK(clbm::launch_batch2(g.storage, b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key, g.small, p, gs));
             continue;
         }
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);

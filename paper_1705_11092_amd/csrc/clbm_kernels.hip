@@ -289,19 +289,23 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
 
 bool step2_supported(const LatDesc &d)
 {
-    return !d.inplace && d.storage == ST_F32 && d.force_mode != FM_SC;
+    return !d.inplace && (d.storage == ST_F32 || d.storage == ST_F64) && d.force_mode != FM_SC;
 }
 
 hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
 {
     if (!step2_supported(d)) return hipErrorInvalidValue;
-    return launch_step2_st<ST_F32>(d, src, s);
+    return d.storage == ST_F64 ? launch_step2_st<ST_F64>(d, src, s) : launch_step2_st<ST_F32>(d, src, s);
 }
 
-hipError_t launch_batch2(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
-                         int pair, hipStream_t s)
+hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
+                         bool small, int pair, hipStream_t s)
 {
-    return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
+    switch (storage) {
+    case ST_F64: return launch_batch2_st<ST_F64>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_F32: return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)

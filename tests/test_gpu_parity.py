@@ -160,16 +160,18 @@ def test_batch_is_bitwise_equal_to_single():
 
 
 def test_batch_pairs_equal_single_steps():
-    # Two-buffer FP32 lattices in a batch advance two fused steps per launch;
-    # per-lattice step counts may be odd (the last step alone) or span several
-    # graph chunks.  Results equal the batch stepping singly, bitwise, for
-    # every lattice; in-place and 16-bit lattices step singly either way.
+    # Two-buffer FP32 and FP64 lattices in a batch advance two fused steps per
+    # launch; per-lattice step counts may be odd (the last step alone) or span
+    # several graph chunks.  Results equal the batch stepping singly, bitwise,
+    # for every lattice; in-place and 16-bit lattices step singly either way.
     from paper_1705_11092_amd import clbm
     shapes = [(37, 23, 0, "field", "f32", False), (300, 70, 1, "field", "f32", False),
               (64, 32, 1, "const", "f32", False), (130, 40, 0, "kolmogorov", "f32", False),
               (1, 17, 1, "const", "f32", False), (96, 20, 1, "none", "f32", True),
-              (80, 48, 0, "field", "f16", False)]
-    counts = [70, 33, 5, 1, 0, 9, 12]
+              (80, 48, 0, "field", "f16", False), (70, 36, 1, "field", "f64", False),
+              (129, 17, 0, "kolmogorov", "f64", False)]
+    counts = [70, 33, 5, 1, 0, 9, 12, 37, 8]
+    more = [3, 2, 1, 4, 7, 0, 5, 3, 0]
     out = []
     for pairs in (False, True):
         lats = []
@@ -181,10 +183,10 @@ def test_batch_pairs_equal_single_steps():
             lats.append(lat)
         b = clbm.Batch(lats)
         b.step_each(counts)
-        b.step_each([3, 2, 1, 4, 7, 0, 5])
+        b.step_each(more)
         b.step(40)
         out.append([lat.get_populations().cpu().numpy() for lat in lats])
-        assert [lat.steps for lat in lats] == [c1 + c2 + 40 for c1, c2 in zip(counts, [3, 2, 1, 4, 7, 0, 5])]
+        assert [lat.steps for lat in lats] == [c1 + c2 + 40 for c1, c2 in zip(counts, more)]
         b.close()
         for lat in lats:
             lat.close()
@@ -312,7 +314,8 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
             assert np.max(np.abs(out[0][0] - fo)) <= 1e-12, f"{nx}x{ny} against the oracle"
 
 
-@pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl")])
+@pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl"), ("f64", "consistent"),
+                                            ("f64", "guo_lbl")])
 def test_two_step_kernel_matches_one_step(storage, scheme):
     # Two fused steps per launch (step n + 1 on a tile and its halo kept in
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
@@ -339,9 +342,14 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
         for o in out[1:]:
             for a, b in zip(out[0], o):
                 assert np.array_equal(a, b), f"{nx}x{ny} bc={bc} {force} {storage} {scheme}"
+        if storage == "f64" and k in (1, 3, len(CASES) + 2, len(CASES) + 3):
+            # Paired FP64 steps against the oracle directly, 24 steps.
+            sch = oracle.SCHEME_CONSISTENT if scheme == "consistent" else oracle.SCHEME_GUO_LBL
+            fo, _, _, _ = oracle_run(wl, 24, scheme=sch)
+            assert np.max(np.abs(out[1][0] - fo)) <= 1e-12, f"{nx}x{ny} bc={bc} {force} f64 pairs"
     # Lattices the fused kernel does not take step singly and say so.
     wl = _case(40, 24, 0, "field", 990)
-    for st, inplace in (("f64", False), ("f32", True), ("f16", False), ("bf16sr", False)):
+    for st, inplace in (("f64", True), ("f32", True), ("f16", False), ("bf16sr", False)):
         lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
