@@ -222,7 +222,8 @@ struct clbm_handle {
     int64_t resident_max = clbm::kResidentMaxGroups;  // resident kernel up to this many groups
     size_t lds = 0;              // dynamic LDS per block that enforces occ
     size_t lds0 = 0;             // the same for in-place phase-0 steps
-    bool pairs = true;           // two fused steps per launch where supported
+    int pairs = -1;              // two fused steps per launch: 1 where supported,
+                                 // 0 never, -1 the default (pairs_by_default)
     int graph_steps = 64;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -242,7 +243,23 @@ void drop_graphs(clbm_handle *h)
 size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0 ? h->lds0 : h->lds; }
 
 // Whether steps go two per launch (the fused two-step kernel).
-bool use_pairs(const clbm_handle *h) { return h->pairs && clbm::step2_supported(h->d); }
+// Measured on MI355X, graphed steps: FP32 lattices step faster in pairs at
+// every size (64 x 32: 3.6 against 4.3 us per step, two launches becoming
+// one); FP64 ones, whose two-step blocks are fewer per CU and longer, only
+// above 256 tiles of 64 x 16 nodes (256: 6.8 against 6.7 us per step,
+// 512: 9.1 against 14.2).
+bool pairs_by_default(const clbm::LatDesc &d)
+{
+    if (d.storage != CLBM_F64) return true;
+    const int64_t tiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + 15) / 16);
+    return tiles > 256;
+}
+
+bool use_pairs(const clbm_handle *h)
+{
+    if (!clbm::step2_supported(h->d)) return false;
+    return h->pairs < 0 ? pairs_by_default(h->d) : h->pairs != 0;
+}
 
 int build_graph(clbm_handle *h, int parity)
 {
@@ -597,9 +614,9 @@ int clbm_set_step_pairs(clbm_handle *h, int32_t enable)
 {
     g_err.clear();
     if (!h) return fail(CLBM_EINVAL, "handle is NULL");
-    if (enable != 0 && enable != 1) return fail(CLBM_EINVAL, "enable must be 0 or 1");
+    if (enable < -1 || enable > 1) return fail(CLBM_EINVAL, "enable must be -1, 0 or 1");
     drop_graphs(h);
-    h->pairs = enable != 0;
+    h->pairs = enable;
     return CLBM_OK;
 }
 

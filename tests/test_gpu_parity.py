@@ -353,11 +353,21 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
         lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
+    # The default: FP32 in pairs at every size, FP64 above 256 tiles of
+    # 64 x 16 nodes (smaller FP64 lattices step faster singly).
     lat = gpu_lattice(wl, storage)
+    assert lat.step_pairs == (storage == "f32")
+    lat.step_pairs = True
     assert lat.step_pairs
+    lat.step_pairs = None
+    assert lat.step_pairs == (storage == "f32")
     with pytest.raises(clbm.ClbmError):
         clbm._check(clbm.lib.clbm_set_step_pairs(lat.handle, 2))
     lat.close()
+    for nx, ny, expect in ((1024, 256, False), (1030, 300, True)):  # 256 and 323 tiles
+        big = gpu_lattice(_case(nx, ny, 0, "const", 991), storage)
+        assert big.step_pairs == (expect or storage == "f32"), f"{nx}x{ny} {storage}"
+        big.close()
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16sr"])
