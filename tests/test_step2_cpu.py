@@ -1,0 +1,100 @@
+"""Host-side checks of the two-step kernel's index maps (no GPU).
+
+The two-step kernel walks its 64 x 16 tiles in vertical strips of up to 8
+tile columns, collides step n + 1 on each tile's 66 x 18 region (the tile and
+a one-node halo) and writes slot i of a region node straight into the LDS
+entry of the tile node that pulls it (Eq. 10), or, next to a bounce-back
+wall, the node's own reversed slot into the entry its absent neighbour would
+fill.  These tests restate that arithmetic and check that the walk visits
+every tile once and that every LDS entry phase B reads is written exactly
+once, by the source the pull with half-way bounce-back names.
+"""
+import pytest
+
+EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+TW, TH, STRIP = 64, 16, 8
+RW, RH = TW + 2, TH + 2
+
+
+def strip_tile(t, tiles_x, tiles_y, sw):
+    full = tiles_x // sw
+    in_full = full * sw * tiles_y
+    if t < in_full:
+        st, i = divmod(t, sw * tiles_y)
+        ty, c = divmod(i, sw)
+        return st * sw + c, ty
+    w = tiles_x - full * sw
+    ty, c = divmod(t - in_full, w)
+    return full * sw + c, ty
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (64, 16), (65, 17), (300, 70), (1030, 9), (4096, 64),
+                                   (520, 200), (64 * 13, 16 * 5)])
+def test_strip_walk_visits_every_tile_once(nx, ny):
+    tiles_x, tiles_y = (nx + TW - 1) // TW, (ny + TH - 1) // TH
+    sw = min(tiles_x, STRIP)
+    seen = [strip_tile(t, tiles_x, tiles_y, sw) for t in range(tiles_x * tiles_y)]
+    assert sorted(seen) == sorted((x, y) for x in range(tiles_x) for y in range(tiles_y))
+    # Within a full strip the tile above is sw tiles earlier.
+    if tiles_y > 1 and tiles_x >= sw:
+        assert seen[sw] == (seen[0][0], seen[0][1] + 1)
+
+
+def _phase_a_writes(nx, ny, bc, x0, y0):
+    """Map (slot, tile row, tile column) -> (source x, source y, source slot)
+    as phase A writes it, from the region's row and column tables."""
+    rows = []
+    for rr in range(RH):
+        y = y0 - 1 + rr
+        beyond = bool(bc) and (y < 0 or y >= ny)
+        if beyond:
+            y = 0 if y < 0 else ny - 1
+        rows.append((y % ny, beyond))
+    cols = [(x0 - 1 + cc) % nx for cc in range(RW)]
+    writes = {}
+    for rr in range(RH):
+        y, beyond = rows[rr]
+        if beyond:
+            continue
+        for cc in range(RW):
+            x = cols[cc]
+            a, b = rr - 1, cc - 1
+            for i in range(9):
+                ai, bi = a + EY[i], b + EX[i]
+                if 0 <= ai < TH and 0 <= bi < TW:
+                    assert (i, ai, bi) not in writes, "written twice"
+                    writes[(i, ai, bi)] = (x, y, i)
+            lo, hi = bc and y == 0, bc and y == ny - 1
+            if (lo or hi) and 0 <= a < TH and 0 <= b < TW:
+                for i in range(9):
+                    if (EY[i] == 1 and lo) or (EY[i] == -1 and hi):
+                        assert (i, a, b) not in writes, "wall entry written twice"
+                        writes[(i, a, b)] = (x, y, OPP[i])
+    return writes
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(300, 70, 1), (300, 70, 0), (65, 17, 1), (33, 1, 1), (70, 2, 1),
+                                      (2, 2, 0), (19, 1, 0), (1, 17, 1), (129, 33, 1), (200, 40, 0)])
+def test_lds_entries_hold_the_pulled_values(nx, ny, bc):
+    tiles_x, tiles_y = (nx + TW - 1) // TW, (ny + TH - 1) // TH
+    for ty in range(tiles_y):
+        for tx in range(tiles_x):
+            x0, y0 = tx * TW, ty * TH
+            writes = _phase_a_writes(nx, ny, bc, x0, y0)
+            for r in range(TH):
+                y = y0 + r
+                if y >= ny:
+                    continue
+                for c in range(TW):
+                    x = x0 + c
+                    if x >= nx:
+                        continue
+                    for i in range(9):
+                        ys = y - EY[i]
+                        if bc and (ys < 0 or ys >= ny):
+                            want = (x, y, OPP[i])  # half-way bounce-back
+                        else:
+                            want = ((x - EX[i]) % nx, ys % ny, i)
+                        assert writes.get((i, r, c)) == want, (nx, ny, bc, tx, ty, r, c, i)
