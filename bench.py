@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the main lattice (16-bit, batch and served legs skipped)")
+    ap.add_argument("--single-steps", action="store_true",
+                    help="step the main lattice one step per launch (no fused pairs)")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--traffic-summary", nargs=4, default=None,
@@ -316,7 +318,7 @@ def main():
               "exchange per step.", file=sys.stderr)
         sys.exit(2)
 
-    ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup)
+    ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=not args.single_steps)
     pairs = run_gpu.pairs
     nodes = args.n * args.n
     ms_step = ms / args.steps
