@@ -58,18 +58,18 @@ def test_largest_square_lattice_fp16():
     assert abs(tot[0] - float(N) * N) <= 1e-6 * N * N
 
 
-def test_two_step_kernel_above_4gb_fp32():
-    # An FP32 lattice whose buffers exceed 4 GB (11000^2: 4.36 GB each) takes
-    # the two-step kernel's 64-bit addressing; its result must equal single
-    # steps bitwise (fields compared on the device).
+@pytest.mark.parametrize("storage,n", [("f32", 11000), ("f64", 7800)])
+def test_two_step_kernel_above_4gb(storage, n):
+    # A lattice whose buffers exceed 4 GB (FP32 11000^2: 4.36 GB each, FP64
+    # 7800^2: 4.38 GB) takes the two-step kernel's 64-bit addressing; its
+    # result must equal single steps bitwise (fields compared on the device).
     import torch
     from paper_1705_11092_amd import clbm
-    n = 11000
-    assert clbm.buffer_bytes(n, n, "f32") > 2**32
+    assert clbm.buffer_bytes(n, n, storage) > 2**32
     rates = (1.0, 1.0, 1.25, 1.25, 1.0, 1.0)
     out = []
     for pairs in (False, True):
-        lat = clbm.Lattice(n, n, rates, storage="f32", bc_y="bounceback")
+        lat = clbm.Lattice(n, n, rates, storage=storage, bc_y="bounceback")
         lat.set_force("kolmogorov", params=(1e-4, 2))
         lat.init()
         lat.step_pairs = pairs
@@ -79,7 +79,7 @@ def test_two_step_kernel_above_4gb_fp32():
         out.append((rho, ux, uy))
         lat.close()
         del lat
-    log(f"{n}^2 f32, 5 steps: pairs vs single steps compared on the device")
+    log(f"{n}^2 {storage}, 5 steps: pairs vs single steps compared on the device")
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
     del out
