@@ -289,13 +289,21 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
 
 bool step2_supported(const LatDesc &d)
 {
-    return !d.inplace && (d.storage == ST_F32 || d.storage == ST_F64) && d.force_mode != FM_SC;
+    return !d.inplace &&
+           (d.storage == ST_F32 || d.storage == ST_F64 || d.storage == ST_F16 || d.storage == ST_BF16) &&
+           d.force_mode != FM_SC;
 }
 
 hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
 {
     if (!step2_supported(d)) return hipErrorInvalidValue;
-    return d.storage == ST_F64 ? launch_step2_st<ST_F64>(d, src, s) : launch_step2_st<ST_F32>(d, src, s);
+    switch (d.storage) {
+    case ST_F64: return launch_step2_st<ST_F64>(d, src, s);
+    case ST_F32: return launch_step2_st<ST_F32>(d, src, s);
+    case ST_F16: return launch_step2_st<ST_F16>(d, src, s);
+    case ST_BF16: return launch_step2_st<ST_BF16>(d, src, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
@@ -304,6 +312,8 @@ hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_l
     switch (storage) {
     case ST_F64: return launch_batch2_st<ST_F64>(lats, tile_lat, ntiles, key, small, pair, s);
     case ST_F32: return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_F16: return launch_batch2_st<ST_F16>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_BF16: return launch_batch2_st<ST_BF16>(lats, tile_lat, ntiles, key, small, pair, s);
     default: return hipErrorInvalidValue;
     }
 }

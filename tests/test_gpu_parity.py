@@ -315,7 +315,7 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
 
 
 @pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl"), ("f64", "consistent"),
-                                            ("f64", "guo_lbl")])
+                                            ("f64", "guo_lbl"), ("f16", "consistent"), ("bf16", "guo_lbl")])
 def test_two_step_kernel_matches_one_step(storage, scheme):
     # Two fused steps per launch (step n + 1 on a tile and its halo kept in
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
@@ -349,24 +349,24 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
             assert np.max(np.abs(out[1][0] - fo)) <= 1e-12, f"{nx}x{ny} bc={bc} {force} f64 pairs"
     # Lattices the fused kernel does not take step singly and say so.
     wl = _case(40, 24, 0, "field", 990)
-    for st, inplace in (("f64", True), ("f32", True), ("f16", False), ("bf16sr", False)):
+    for st, inplace in (("f64", True), ("f32", True), ("f16", True), ("f16sr", False), ("bf16sr", False)):
         lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
     # The default: FP32 in pairs at every size, FP64 above 256 tiles of
     # 64 x 16 nodes (smaller FP64 lattices step faster singly).
     lat = gpu_lattice(wl, storage)
-    assert lat.step_pairs == (storage == "f32")
+    assert lat.step_pairs == (storage != "f64")
     lat.step_pairs = True
     assert lat.step_pairs
     lat.step_pairs = None
-    assert lat.step_pairs == (storage == "f32")
+    assert lat.step_pairs == (storage != "f64")
     with pytest.raises(clbm.ClbmError):
         clbm._check(clbm.lib.clbm_set_step_pairs(lat.handle, 2))
     lat.close()
     for nx, ny, expect in ((1024, 256, False), (1030, 300, True)):  # 256 and 323 tiles
         big = gpu_lattice(_case(nx, ny, 0, "const", 991), storage)
-        assert big.step_pairs == (expect or storage == "f32"), f"{nx}x{ny} {storage}"
+        assert big.step_pairs == (expect or storage != "f64"), f"{nx}x{ny} {storage}"
         big.close()
 
 
