@@ -245,8 +245,8 @@ size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0
 // Whether steps go two per launch (the fused two-step kernel).
 // Measured on MI355X, graphed steps: FP32 lattices step faster in pairs at
 // every size (64 x 32: 3.6 against 4.3 us per step, two launches becoming
-// one), and so do FP16 and BF16 ones at 4096^2 (163.5 and 161.6 against
-// 149.7 and 152.8 GLUPS); FP64 ones, whose two-step blocks are fewer per CU
+// one), and so do the 16-bit ones at 4096^2 (FP16 163.5 against 149.7
+// GLUPS, FP16 with stochastic rounding 160.3 against 150.9); FP64 ones, whose two-step blocks are fewer per CU
 // and longer, only above 256 tiles of 64 x 16 nodes (256: 6.8 against 6.7
 // us per step, 512: 9.1 against 14.2).
 bool pairs_by_default(const clbm::LatDesc &d)

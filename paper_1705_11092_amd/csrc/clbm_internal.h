@@ -121,14 +121,13 @@ hipError_t launch_tile_map(const LatDesc *lats, int l_lo, int l_hi, int64_t ntil
 // block; vec is the storage type's default nodes per thread.
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s);
 // Two fused steps (temporal blocking) from buffer src into src ^ 1: two
-// buffers, FP64, FP32, FP16 or BF16 storage, any force but Shan-Chen
-// (step2_supported).
+// buffers, any storage type, any force but Shan-Chen (step2_supported).
 bool step2_supported(const LatDesc &d);
 hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s);
 // Pair substep `pair` of a batch group whose lattices step in pairs: each
 // lattice with at least 2 pair + 2 steps left takes two fused steps, one
 // with 2 pair + 1 left takes its last single step.  small: every buffer of
-// the group is below 4 GB; storage is the group's (FP64, FP32, FP16, BF16).
+// the group is below 4 GB; storage is the group's.
 hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
                          bool small, int pair, hipStream_t s);
 // The same per storage type, one translation unit each (clbm_step_*.hip).

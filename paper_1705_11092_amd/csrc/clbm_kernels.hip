@@ -290,7 +290,8 @@ hipError_t launch_step(const LatDesc &d, int src, int vec, size_t lds, hipStream
 bool step2_supported(const LatDesc &d)
 {
     return !d.inplace &&
-           (d.storage == ST_F32 || d.storage == ST_F64 || d.storage == ST_F16 || d.storage == ST_BF16) &&
+           (d.storage == ST_F32 || d.storage == ST_F64 || d.storage == ST_F16 || d.storage == ST_BF16 ||
+            d.storage == ST_F16_SR || d.storage == ST_BF16_SR) &&
            d.force_mode != FM_SC;
 }
 
@@ -302,6 +303,8 @@ hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
     case ST_F32: return launch_step2_st<ST_F32>(d, src, s);
     case ST_F16: return launch_step2_st<ST_F16>(d, src, s);
     case ST_BF16: return launch_step2_st<ST_BF16>(d, src, s);
+    case ST_F16_SR: return launch_step2_st<ST_F16_SR>(d, src, s);
+    case ST_BF16_SR: return launch_step2_st<ST_BF16_SR>(d, src, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -314,6 +317,8 @@ hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_l
     case ST_F32: return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
     case ST_F16: return launch_batch2_st<ST_F16>(lats, tile_lat, ntiles, key, small, pair, s);
     case ST_BF16: return launch_batch2_st<ST_BF16>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_F16_SR: return launch_batch2_st<ST_F16_SR>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_BF16_SR: return launch_batch2_st<ST_BF16_SR>(lats, tile_lat, ntiles, key, small, pair, s);
     default: return hipErrorInvalidValue;
     }
 }

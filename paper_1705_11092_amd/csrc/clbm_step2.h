@@ -201,6 +201,19 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         force_at<R, FM>(d, xa[m], ya[m], Fx, Fy);
         collide<R, SCH>(ga[m], Fx, Fy, rt);
         if (keep[m]) {
+            // Each value in its storage type as the one-step kernel stores
+            // it: rounded to nearest, or stochastically with the operand of
+            // the node's hash (its index and its post-collision slot 0).
+            T rv[9];
+            if constexpr (S::kDither) {
+                const uint32_t node = (uint32_t)ya[m] * (uint32_t)d.nx + (uint32_t)xa[m];
+                const uint32_t h = hash32(__float_as_uint(ga[m][0]) ^ (node * 0x9e3779b9u));
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rv[i] = S::from_r_sr(ga[m][i], sr_operand(h, i));
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rv[i] = S::from_r(ga[m][i]);
+            }
             // Tile coordinates of the node; slot i goes to the tile node
             // that pulls it, (a + e_y,i, b + e_x,i), when that node is in
             // the tile.
@@ -208,7 +221,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int ai = a + ey_of(i), bi = b + ex_of(i);
-                if (ai >= 0 && ai < kTH && bi >= 0 && bi < kTW) lds[i][ai][bi] = S::from_r(ga[m][i]);
+                if (ai >= 0 && ai < kTH && bi >= 0 && bi < kTW) lds[i][ai][bi] = rv[i];
             }
             // Next to a wall the node's slots that would come from beyond
             // it take the node's own reversed values (nothing else is
@@ -218,7 +231,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     if ((ey_of(i) == 1 && lo) || (ey_of(i) == -1 && hi))
-                        lds[i][a][b] = S::from_r(ga[m][opp_of(i)]);
+                        lds[i][a][b] = rv[opp_of(i)];
                 }
             }
         }
@@ -243,8 +256,29 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         R Fx, Fy;
         force_at<R, FM>(d, x0 + c + k < d.nx ? x0 + c + k : d.nx - 1, y, Fx, Fy);
         collide<R, SCH>(g[k], Fx, Fy, rt);
+    }
+    if constexpr (S::kDither) {
+        // The one-step kernel's stochastic rounding of four nodes, in pairs.
+        uint32_t h[4];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) q[i].v[k] = S::from_r(g[k][i]);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + c + k);
+            h[k] = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+#pragma unroll
+            for (int k = 0; k < 4; k += 2) {
+                const auto two = S::from_r_sr2(g[k][i], sr_operand(h[k], i), g[k + 1][i], sr_operand(h[k + 1], i));
+                q[i].v[k] = two[0];
+                q[i].v[k + 1] = two[1];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) q[i].v[k] = S::from_r(g[k][i]);
     }
     const I ob = row_at<I>(d, y) + (I)(x0 + c);
     if (x0 + c + 4 <= d.nx) {

@@ -315,7 +315,8 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
 
 
 @pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl"), ("f64", "consistent"),
-                                            ("f64", "guo_lbl"), ("f16", "consistent"), ("bf16", "guo_lbl")])
+                                            ("f64", "guo_lbl"), ("f16", "consistent"), ("bf16", "guo_lbl"),
+                                            ("f16sr", "consistent"), ("bf16sr", "guo_lbl")])
 def test_two_step_kernel_matches_one_step(storage, scheme):
     # Two fused steps per launch (step n + 1 on a tile and its halo kept in
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
@@ -349,7 +350,7 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
             assert np.max(np.abs(out[1][0] - fo)) <= 1e-12, f"{nx}x{ny} bc={bc} {force} f64 pairs"
     # Lattices the fused kernel does not take step singly and say so.
     wl = _case(40, 24, 0, "field", 990)
-    for st, inplace in (("f64", True), ("f32", True), ("f16", True), ("f16sr", False), ("bf16sr", False)):
+    for st, inplace in (("f64", True), ("f32", True), ("f16", True), ("bf16sr", True)):
         lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
