@@ -160,10 +160,11 @@ def test_batch_is_bitwise_equal_to_single():
 
 
 def test_batch_pairs_equal_single_steps():
-    # Two-buffer FP32 and FP64 lattices in a batch advance two fused steps per
-    # launch; per-lattice step counts may be odd (the last step alone) or span
-    # several graph chunks.  Results equal the batch stepping singly, bitwise,
-    # for every lattice; in-place and 16-bit lattices step singly either way.
+    # Two-buffer lattices (FP32, FP64 and FP16 here) in a batch advance two
+    # fused steps per launch; per-lattice step counts may be odd (the last
+    # step alone) or span several graph chunks.  Results equal the batch
+    # stepping singly, bitwise, for every lattice; in-place lattices step
+    # singly either way.
     from paper_1705_11092_amd import clbm
     shapes = [(37, 23, 0, "field", "f32", False), (300, 70, 1, "field", "f32", False),
               (64, 32, 1, "const", "f32", False), (130, 40, 0, "kolmogorov", "f32", False),
