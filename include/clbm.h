@@ -174,7 +174,7 @@ int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double 
  * kernel launch per step (two buffers: each node gathers its pre-collision
  * populations from its neighbours' post-collision ones; in place: the AA
  * pattern of clbm_streaming).  Two-buffer FP32 and 16-bit lattices and FP64
- * lattices of more than 256 tiles of 64 x 16 nodes (any force but
+ * lattices of at least 128 tiles of 64 x 16 nodes (any force but
  * Shan-Chen) advance two steps per launch by default (clbm_set_step_pairs),
  * with bitwise the same result.  Long runs replay a captured hipGraph.
  * Errors: CLBM_ESTATE before clbm_init or clbm_set_populations, CLBM_EINVAL
@@ -231,7 +231,7 @@ int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu);
  * operand depends on its index and values only).  Applies to two-buffer
  * lattices of every storage type without the Shan-Chen force; in-place
  * lattices always step singly.  The default, from measurements on MI355X:
- * pairs for FP32 and the 16-bit types at every size, for FP64 above 256
+ * pairs for FP32 and the 16-bit types at every size, for FP64 from 128
  * tiles (smaller FP64 lattices step faster singly).  clbm_get_step_pairs
  * returns 1 when this lattice steps in pairs, 0 when not, -1 for NULL.
  * Errors: CLBM_EINVAL (NULL handle, enable not -1, 0 or 1). */

@@ -243,17 +243,17 @@ void drop_graphs(clbm_handle *h)
 size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0 ? h->lds0 : h->lds; }
 
 // Whether steps go two per launch (the fused two-step kernel).
-// Measured on MI355X, graphed steps: FP32 lattices step faster in pairs at
-// every size (64 x 32: 3.6 against 4.3 us per step, two launches becoming
-// one), and so do the 16-bit ones at 4096^2 (FP16 163.5 against 149.7
-// GLUPS, FP16 with stochastic rounding 160.3 against 150.9); FP64 ones, whose two-step blocks are fewer per CU
-// and longer, only above 256 tiles of 64 x 16 nodes (256: 6.8 against 6.7
-// us per step, 512: 9.1 against 14.2).
+// Measured on MI355X, graphed steps: FP32 and 16-bit lattices step faster
+// in pairs at every size (64 x 32: FP32 3.6 against 4.3 us per step, FP16
+// 3.7 against 4.3, two launches becoming one); FP64 ones, whose two-step
+// blocks are fewer per CU and longer, only from 128 tiles of 64 x 16 nodes
+// (64 tiles: 4.7 against 4.3 us per step, 128: 5.0 against 5.2, 512: 8.8
+// against 14.3).
 bool pairs_by_default(const clbm::LatDesc &d)
 {
     if (d.storage != CLBM_F64) return true;
     const int64_t tiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + 15) / 16);
-    return tiles > 256;
+    return tiles >= 128;
 }
 
 bool use_pairs(const clbm_handle *h)

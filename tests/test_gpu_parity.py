@@ -355,8 +355,8 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
         lat = gpu_lattice(wl, st, inplace=inplace)
         assert not lat.step_pairs
         lat.close()
-    # The default: FP32 in pairs at every size, FP64 above 256 tiles of
-    # 64 x 16 nodes (smaller FP64 lattices step faster singly).
+    # The default: FP32 and 16-bit in pairs at every size, FP64 from 128
+    # tiles of 64 x 16 nodes (smaller FP64 lattices step faster singly).
     lat = gpu_lattice(wl, storage)
     assert lat.step_pairs == (storage != "f64")
     lat.step_pairs = True
@@ -366,7 +366,7 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
     with pytest.raises(clbm.ClbmError):
         clbm._check(clbm.lib.clbm_set_step_pairs(lat.handle, 2))
     lat.close()
-    for nx, ny, expect in ((1024, 256, False), (1030, 300, True)):  # 256 and 323 tiles
+    for nx, ny, expect in ((512, 192, False), (512, 256, True)):  # 96 and 128 tiles
         big = gpu_lattice(_case(nx, ny, 0, "const", 991), storage)
         assert big.step_pairs == (expect or storage != "f64"), f"{nx}x{ny} {storage}"
         big.close()
