@@ -23,10 +23,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "clbm_oracle.c")
 _LIB = os.path.join(_HERE, "libclbm_oracle.so")
 
-#: Forcing schemes: Eq. (12) (the paper's) and Eq. (21) (Lycett-Brown & Luo
-#: with Guo's term).
+#: Forcing schemes: Eq. (12) (the paper's), Eq. (21) (Lycett-Brown & Luo
+#: with Guo's term) and Eqs. (17)-(19) (Premnath et al., Sec. III A).
 SCHEME_CONSISTENT = 0
 SCHEME_GUO_LBL = 1
+SCHEME_PREMNATH = 2
 
 BC_PERIODIC = 0
 BC_BOUNCEBACK = 1
@@ -59,6 +60,7 @@ def _load():
     lib.oracle_matrix_N.argtypes = [dbl, dbl, dp]
     lib.oracle_matrix_Ninv.argtypes = [dbl, dbl, dp]
     lib.oracle_collide.argtypes = [dp, dbl, dbl, dp, i32, i32, dp]
+    lib.oracle_premnath_delta_f.argtypes = [dbl, dbl, dbl, dbl, dp]
     lib.oracle_step.argtypes = [i32, i32, i32, dp, i32, dp, dp, dp, dp, i32]
     lib.oracle_step.restype = i32
     lib.oracle_run.argtypes = [i32, i32, i32, dp, i32, dp, dp, dp, dp, i64, i32]
@@ -129,6 +131,14 @@ def collide(f, Fx: float, Fy: float, s, scheme: int = SCHEME_CONSISTENT,
     out = np.empty(9)
     _load().oracle_collide(_p(f), float(Fx), float(Fy), _p(s), int(scheme),
                            1 if shift else 0, _p(out))
+    return out
+
+
+def premnath_delta_f(Fx: float, Fy: float, ux: float, uy: float) -> np.ndarray:
+    """Delta f_i of Sec. III A (Eq. 18) at velocity u: the discrete
+    distribution whose central moments are C_P of Eq. (19)."""
+    out = np.empty(9)
+    _load().oracle_premnath_delta_f(float(Fx), float(Fy), float(ux), float(uy), _p(out))
     return out
 
 

@@ -211,8 +211,36 @@ static const double W[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 /* Forcing schemes the oracle knows. */
 enum {
     ORACLE_SCHEME_CONSISTENT = 0, /* Eq. (12) with C from Eq. (14)       */
-    ORACLE_SCHEME_GUO_LBL = 1     /* Eq. (21): (1 - s2/2) N M R_G        */
+    ORACLE_SCHEME_GUO_LBL = 1,    /* Eq. (21): (1 - s2/2) N M R_G        */
+    ORACLE_SCHEME_PREMNATH = 2    /* Eqs. (17)-(19), Sec. III A          */
 };
+
+/*
+ * Sec. III A (Premnath et al.): the central moments of the force's change
+ * of the distribution, with the higher-order ones dropped (Eq. 19):
+ * C_P = [0, Fx, Fy, 0, 0, 0, 0, 0, 0].  The paper cites the discrete
+ * change Delta f_i without printing it; it is read here as the discrete
+ * distribution whose central moments about u are exactly C_P, i.e.
+ * Delta f = M^-1 N^-1(u) C_P.  That reading gives the leading term of
+ * Eq. (20), Delta f_0 = -2 F.u + O(u^3), and makes the scheme coincide
+ * with Eq. (12) at s3 = 2 (Remark 6).
+ */
+static void premnath_moments(double Fx, double Fy, double CP[Q])
+{
+    memset(CP, 0, sizeof(double) * Q);
+    CP[1] = Fx;
+    CP[2] = Fy;
+}
+
+/* Delta f_i of Sec. III A at velocity u (the reading above). */
+static void premnath_delta_f(double Fx, double Fy, double ux, double uy, double df[Q])
+{
+    double CP[Q], NI[Q][Q], T[Q];
+    premnath_moments(Fx, Fy, CP);
+    shift_matrix_inverse(ux, uy, NI);
+    matvec(NI, CP, T);
+    matvec(MINV, T, df);
+}
 
 /* Guo's forcing term R_Gi (Remark 3) at velocity u. */
 static void guo_force_term(double Fx, double Fy, double ux, double uy, double R[Q])
@@ -280,6 +308,10 @@ static void collide(const double f[Q], double Fx, double Fy, const double s6[6],
         matvec(N, MR, CG);
     }
 
+    /* Eq. (19): the force's central moments in the scheme of Sec. III A. */
+    double CP[Q];
+    premnath_moments(Fx, Fy, CP);
+
     if (!shift) {
         /* Remark 2: with N = I the same vectors are expressed as raw moments. */
         double tmp[Q];
@@ -291,11 +323,18 @@ static void collide(const double f[Q], double Fx, double Fy, const double s6[6],
             matvec(NI, CG, tmp);
             memcpy(CG, tmp, sizeof tmp);
         }
+        matvec(NI, CP, tmp);
+        memcpy(CP, tmp, sizeof tmp);
     }
 
-    /* Eq. (12) first line (consistent), or Eq. (21) (Lycett-Brown & Luo). */
+    /* Eq. (12) first line (consistent), Eq. (21) (Lycett-Brown & Luo), or
+     * Eq. (17) (Premnath et al.: relaxation toward T~eq - C_P/2). */
     double Ts[Q];
     for (int k = 0; k < Q; ++k) {
+        if (scheme == ORACLE_SCHEME_PREMNATH) {
+            Ts[k] = (1.0 - S[k]) * Tt[k] + S[k] * (Teq[k] - CP[k] / 2.0);
+            continue;
+        }
         Ts[k] = (1.0 - S[k]) * Tt[k] + S[k] * Teq[k];
         if (scheme == ORACLE_SCHEME_GUO_LBL)
             Ts[k] += (1.0 - s6[3] / 2.0) * CG[k];
@@ -310,6 +349,18 @@ static void collide(const double f[Q], double Fx, double Fy, const double s6[6],
     else
         memcpy(Tr, Ts, sizeof Ts);
     matvec(MINV, Tr, fout);
+
+    /* Eq. (18): the scheme of Sec. III A adds the discrete change Delta f
+     * (CP already holds raw moments when N = I). */
+    if (scheme == ORACLE_SCHEME_PREMNATH) {
+        double df[Q];
+        if (shift) {
+            premnath_delta_f(Fx, Fy, ux, uy, df);
+        } else {
+            matvec(MINV, CP, df);
+        }
+        for (int i = 0; i < Q; ++i) fout[i] += df[i];
+    }
 }
 
 /* ----------------------------------------------------------------------- */
@@ -338,6 +389,12 @@ void oracle_matrix_Ninv(double ux, double uy, double *out)
     double NI[Q][Q];
     shift_matrix_inverse(ux, uy, NI);
     memcpy(out, NI, sizeof NI);
+}
+
+/* Delta f_i of Sec. III A (Eq. 18) at velocity u. */
+void oracle_premnath_delta_f(double Fx, double Fy, double ux, double uy, double *out)
+{
+    premnath_delta_f(Fx, Fy, ux, uy, out);
 }
 
 /* One collision at one node (see collide()). */
