@@ -92,8 +92,20 @@ typedef enum { CLBM_STREAM_TWO_BUFFERS = 0, CLBM_STREAM_IN_PLACE = 1 } clbm_stre
 
 /* Forcing scheme.  CONSISTENT is the paper's (Eq. 12).  GUO_LBL is the
  * Lycett-Brown & Luo scheme with Guo's term (Eq. 21), kept for the paper's
- * comparisons; it needs s1 = s2 to conserve momentum (Remark 5). */
-typedef enum { CLBM_SCHEME_CONSISTENT = 0, CLBM_SCHEME_GUO_LBL = 1 } clbm_scheme;
+ * comparisons; it needs s1 = s2 to conserve momentum (Remark 5).  PREMNATH
+ * is the scheme of Premnath et al. as Sec. III A writes it (Eqs. 17-19):
+ * relaxation toward T~eq - C_P/2 with C_P = [0, Fx, Fy, 0, ..., 0], then
+ * the discrete change Delta f added after the back-transform, read as
+ * Delta f = M^-1 N^-1(u) C_P (the distribution whose central moments are
+ * C_P; it gives Eq. 20's Delta f_0 = -2 F.u + O(u^3)).  That equals
+ * Eq. (12) with the third-order force moments of Eq. (14) removed, which is
+ * how it runs: the consistent kernel with their weight 1 - s3/2 set to zero
+ * (Remark 6: the two coincide at s3 = 2).  s0 and s1 are free (Remark 5). */
+typedef enum {
+    CLBM_SCHEME_CONSISTENT = 0,
+    CLBM_SCHEME_GUO_LBL = 1,
+    CLBM_SCHEME_PREMNATH = 2
+} clbm_scheme;
 
 /* ---- single lattice ---------------------------------------------------- */
 

@@ -21,7 +21,7 @@ ELEM_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f16sr": 2, "bf16sr": 2}
 BC = {"periodic": 0, "bounceback": 1}
 STREAM_TWO_BUFFERS, STREAM_IN_PLACE = 0, 1
 FORCE = {"none": 0, "const": 1, "kolmogorov": 2, "field": 3, "shan_chen": 4}
-SCHEME = {"consistent": 0, "guo_lbl": 1}
+SCHEME = {"consistent": 0, "guo_lbl": 1, "premnath": 2}
 
 CLBM_OK, CLBM_EINVAL, CLBM_EHIP, CLBM_ESTATE, CLBM_ENONFINITE = 0, -1, -2, -3, -4
 

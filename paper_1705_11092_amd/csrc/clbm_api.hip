@@ -318,7 +318,8 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     if (cfg->bc_y != CLBM_Y_PERIODIC && cfg->bc_y != CLBM_Y_BOUNCEBACK)
         return fail(CLBM_EINVAL, "bc_y must be CLBM_Y_PERIODIC or CLBM_Y_BOUNCEBACK");
     if (elem_bytes(cfg->storage) == 0) return fail(CLBM_EINVAL, "unknown storage");
-    if (cfg->scheme != CLBM_SCHEME_CONSISTENT && cfg->scheme != CLBM_SCHEME_GUO_LBL)
+    if (cfg->scheme != CLBM_SCHEME_CONSISTENT && cfg->scheme != CLBM_SCHEME_GUO_LBL &&
+        cfg->scheme != CLBM_SCHEME_PREMNATH)
         return fail(CLBM_EINVAL, "unknown scheme");
     if (cfg->streaming != CLBM_STREAM_TWO_BUFFERS && cfg->streaming != CLBM_STREAM_IN_PLACE)
         return fail(CLBM_EINVAL, "streaming must be CLBM_STREAM_TWO_BUFFERS or CLBM_STREAM_IN_PLACE");
@@ -351,14 +352,17 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.bc_y = cfg->bc_y;
     d.storage = cfg->storage;
     d.force_mode = clbm::FM_CONST;
-    d.scheme = cfg->scheme;
+    // Premnath et al.'s scheme (Sec. III A) is Eq. (12) without the
+    // third-order force moments: the consistent kernel with their weight
+    // (1 - s3/2) zero.
+    d.scheme = cfg->scheme == CLBM_SCHEME_GUO_LBL ? clbm::SCH_GUO_LBL : clbm::SCH_CONSISTENT;
     d.rho0 = cfg->rho0;
     d.om1 = 1.0 - cfg->s1;
     d.omb = 1.0 - cfg->sb;
     d.om2 = 1.0 - cfg->s2;
     d.om3 = 1.0 - cfg->s3;
     d.om4 = 1.0 - cfg->s4;
-    d.h3 = 1.0 - 0.5 * cfg->s3;
+    d.h3 = cfg->scheme == CLBM_SCHEME_PREMNATH ? 0.0 : 1.0 - 0.5 * cfg->s3;
     d.h2 = 1.0 - 0.5 * cfg->s2;
     h->vec = default_vec(cfg->storage);
     h->occ = default_occupancy(cfg->storage, 2 * need, inplace, 1);
@@ -784,9 +788,9 @@ void batch_geometry(clbm_batch *b)
 
 // Refresh the table from the lattices (force, parity) with the steps each
 // takes in this call, and send it to the device through kernel arguments.
-// With `scratch`, in-place lattices write there instead of into their state
+// With `spare`, in-place lattices write there instead of into their state
 // (the autotuner's timed launches).
-int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
+int batch_upload(clbm_batch *b, const int64_t *nsteps, void *spare = nullptr)
 {
     clbm::UploadPayload p;
     const int count = (int)b->order.size();
@@ -805,7 +809,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *scratch = nullptr)
             d.pairs = g.pairs;
             d.parity = h->parity;
             d.steps = (int32_t)nsteps[b->order[pos]];
-            if (scratch && d.inplace) d.buf[1] = scratch;
+            if (spare && d.inplace) d.buf[1] = spare;
             p.d[k] = d;
         }
         HIPCHK(clbm::launch_upload(b->d_lats, first, n, p, b->stream));
@@ -1075,13 +1079,12 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     // launches write one scratch allocation as large as the largest of
     // them (all into the same place; its contents are never read).
     std::vector<int64_t> ones(b->lats.size(), 1);
-    size_t scratch_bytes = 0;
+    size_t spare_bytes = 0;
     for (auto *h : b->lats)
         if (h->d.inplace)
-            scratch_bytes = std::max(scratch_bytes,
-                                     clbm_buffer_bytes(h->d.nx, h->d.ny, h->d.storage));
-    void *scratch = nullptr;
-    if (scratch_bytes) HIPCHK(hipMallocAsync(&scratch, scratch_bytes, b->stream));
+            spare_bytes = std::max(spare_bytes, clbm_buffer_bytes(h->d.nx, h->d.ny, h->d.storage));
+    void *spare = nullptr;
+    if (spare_bytes) HIPCHK(hipMallocAsync(&spare, spare_bytes, b->stream));
     hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
@@ -1090,7 +1093,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     int rc = CLBM_OK;
     for (int v = 0; v < kNumVariants && rc == CLBM_OK; ++v) {
         if ((rc = clbm_batch_set_variant(b, v))) break;
-        if ((rc = batch_upload(b, ones.data(), scratch))) break;
+        if ((rc = batch_upload(b, ones.data(), spare))) break;
         const int reps = 5;
         for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_steps(b, 0, 1, b->stream);
         if (rc) break;
@@ -1113,7 +1116,7 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    if (scratch) (void)hipFreeAsync(scratch, b->stream);
+    if (spare) (void)hipFreeAsync(spare, b->stream);
     if (rc) return rc;
     if ((rc = clbm_batch_set_variant(b, best))) return rc;
     if (chosen) *chosen = best;

