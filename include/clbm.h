@@ -204,6 +204,29 @@ int64_t clbm_step_count(const clbm_handle *h);
  * is NaN or Inf.  Errors: CLBM_ESTATE, CLBM_EHIP, CLBM_ENONFINITE. */
 int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *totals);
 
+/* For callers that cannot allocate memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * fields of clbm_moments, and its FP64 totals, with no allocation of any
+ * kind (device, pinned host or library) and no wait for the device.
+ *   rho, ux, uy : as in clbm_moments (device FP64 [ny][nx] outputs, each
+ *                 may be NULL), the same values bit for bit;
+ *   totals      : DEVICE memory for 3 doubles {sum rho, sum rho ux,
+ *                 sum rho uy}, or NULL; written on the handle's stream, the
+ *                 same values bit for bit as clbm_moments returns.
+ * The call only enqueues work and returns; it does not check the totals
+ * for NaN or Inf (the caller reads them once the stream has passed).
+ * The FP64 partial sums live in a static device array of 24 KB (the
+ * partials of at most 1024 blocks, which is what the moments pass uses for
+ * a lattice of any size), one per GPU, held until the process ends; a
+ * lattice that needed more would be refused with CLBM_EINVAL.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller.
+ * On its first call on a device the library looks up the array's address
+ * there (with that device current).
+ * Errors: CLBM_ESTATE, CLBM_EINVAL (outputs that are not device memory or
+ * too small), CLBM_EHIP. */
+int clbm_moments_noalloc(clbm_handle *h, double *rho, double *ux, double *uy, double *totals);
+
 /* FP64 error norms on the GPU against reference velocity fields ux_ref,
  * uy_ref (device FP64 [ny][nx]): out[0] = sum |u - u_ref|^2 and out[1] =
  * sum |u_ref|^2 over both components and all nodes (host), so that

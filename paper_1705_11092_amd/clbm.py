@@ -66,6 +66,7 @@ def _load():
         "clbm_get_occupancy": (i32, [vp]),
         "clbm_step_count": (i64, [vp]),
         "clbm_moments": (ctypes.c_int, [vp, vp, vp, vp, dp]),
+        "clbm_moments_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "clbm_error_norms": (ctypes.c_int, [vp, vp, vp, dp]),
         "clbm_get_populations": (ctypes.c_int, [vp, vp]),
         "clbm_set_populations": (ctypes.c_int, [vp, vp]),
@@ -94,7 +95,7 @@ lib = _load()
 #: Every symbol include/clbm.h declares.
 EXPORTED = (
     "clbm_buffer_bytes", "clbm_create", "clbm_destroy", "clbm_set_force", "clbm_init",
-    "clbm_step", "clbm_step_count", "clbm_moments", "clbm_error_norms",
+    "clbm_step", "clbm_step_count", "clbm_moments", "clbm_moments_noalloc", "clbm_error_norms",
     "clbm_get_populations", "clbm_set_populations", "clbm_set_graph_steps",
     "clbm_set_occupancy", "clbm_get_occupancy", "clbm_set_resident_limit",
     "clbm_set_step_pairs", "clbm_get_step_pairs",
@@ -263,6 +264,12 @@ class Lattice:
             _check(lib.clbm_moments(self._h, _ptr(rho), _ptr(ux), _ptr(uy),
                                     ctypes.cast(tot, ctypes.POINTER(ctypes.c_double)) if totals else None))
         return rho, ux, uy, (list(tot) if totals else None)
+
+    def moments_noalloc(self, rho=None, ux=None, uy=None, totals=None):
+        """clbm_moments_noalloc into caller-owned FP64 device tensors (each
+        may be None; totals holds 3 values).  Enqueues only: the library
+        allocates nothing and does not wait for the device."""
+        _check(lib.clbm_moments_noalloc(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(totals)))
 
     def error_norms(self, ux_ref, uy_ref):
         """(sum |u - u_ref|^2, sum |u_ref|^2) in FP64 on the GPU."""

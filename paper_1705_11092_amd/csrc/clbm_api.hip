@@ -193,6 +193,41 @@ void retire_graph(hipGraphExec_t g, hipStream_t s)
     g_retired.emplace_back(g, ev);
 }
 
+// Reduction scratch of clbm_moments_noalloc, for callers that cannot
+// allocate: the FP64 partial sums of at most kMomentsMaxBlocks blocks (three
+// components each), 24 KB.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name is only a stand-in: its
+// device address comes from hipGetSymbolAddress, once per device
+// (noalloc_scratch), and only that address is ever handed to a kernel.
+constexpr int kNoAllocScratchDoubles = 3 * clbm::kMomentsMaxBlocks;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+
+// Device address of the current device's copy of `scratch`, looked up on
+// the first call on that device (with it current) and kept.
+int noalloc_scratch(double **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CLBM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(CLBM_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CLBM_OK;
+}
+
 // Pinned host words for the FP64 totals, one set per host thread for the
 // life of the process (the calls that use them wait for their stream).
 double *pinned_words()
@@ -556,6 +591,32 @@ int clbm_moments(clbm_handle *h, double *rho, double *ux, double *uy, double *to
     totals[2] = w[2];
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(totals[c])) return fail(CLBM_ENONFINITE, "mass or momentum is not finite");
+    return CLBM_OK;
+}
+
+int clbm_moments_noalloc(clbm_handle *h, double *rho, double *ux, double *uy, double *totals)
+{
+    g_err.clear();
+    int rc = need_ready(h);
+    if (rc) return rc;
+    const size_t fb = sizeof(double) * (size_t)h->d.nx * h->d.ny;
+    if (rho && (rc = check_device_range(rho, fb, "rho"))) return rc;
+    if (ux && (rc = check_device_range(ux, fb, "ux"))) return rc;
+    if (uy && (rc = check_device_range(uy, fb, "uy"))) return rc;
+    if (totals && (rc = check_device_range(totals, 3 * sizeof(double), "totals"))) return rc;
+    const int nb = clbm::moments_blocks((int64_t)h->d.nx * h->d.ny);
+    if (3 * (int64_t)nb > kNoAllocScratchDoubles)
+        return fail(CLBM_EINVAL, "lattice needs more reduction scratch than the static maximum");
+    double *partials = nullptr;
+    if ((rc = noalloc_scratch(&partials))) return rc;
+    // Every partial is written before it is read: nothing to clear.
+    int used = 0;
+    if (h->d.force_mode == clbm::FM_SC) HIPCHK(clbm::launch_psi(h->d, h->parity, nullptr, h->stream));
+    HIPCHK(clbm::launch_moments(h->d, h->parity, rho, ux, uy, nullptr, nullptr, partials, &used,
+                                h->stream));
+    if (!totals) return CLBM_OK;
+    HIPCHK(clbm::launch_reduce(partials, used, 3, totals, h->stream,
+                               (double)h->d.nx * h->d.ny * h->d.rho0));
     return CLBM_OK;
 }
 

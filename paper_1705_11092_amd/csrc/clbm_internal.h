@@ -154,7 +154,10 @@ hipError_t launch_get_populations(const LatDesc &d, int src, double *f, hipStrea
 hipError_t launch_moments(const LatDesc &d, int src, double *rho, double *ux, double *uy,
                           const double *ux_ref, const double *uy_ref, double *partials,
                           int *nblocks, hipStream_t s);
-hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s);
+// out[c] = the fixed-order sum of component c over the partial blocks, plus
+// base0 for c = 0.
+hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s,
+                         double base0 = 0.0);
 hipError_t launch_force_table(const LatDesc &d, void *table, double A, double k, hipStream_t s);
 hipError_t launch_force_field(const LatDesc &d, void *field, const double *fx, const double *fy,
                               hipStream_t s);
@@ -162,7 +165,9 @@ hipError_t launch_force_field(const LatDesc &d, void *field, const double *fx, c
 // state in buffer src, or (rho != NULL) from a given density field, or
 // (src < 0, rho == NULL) from the rest density.
 hipError_t launch_psi(const LatDesc &d, int src, const double *rho, hipStream_t s);
-// Partial blocks the moments kernel uses for a lattice of n nodes.
+// Partial blocks the moments kernel uses for a lattice of n nodes (at most
+// kMomentsMaxBlocks, whatever n).
+constexpr int kMomentsMaxBlocks = 1024;
 int moments_blocks(int64_t n);
 
 }  // namespace clbm

@@ -231,14 +231,16 @@ __global__ __launch_bounds__(kBlock) void k_moments(LatDesc d, int src, double *
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int nblocks, int ncomp,
-                                                   double *out)
+                                                   double *out, double base0)
 {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += kBlock)
         for (int c = 0; c < ncomp; ++c) acc[c] += partials[3 * b + c];
     block_sum<3>(acc);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        acc[0] += base0;
         for (int c = 0; c < ncomp; ++c) out[c] = acc[c];
+    }
 }
 
 template <typename R>
@@ -415,7 +417,7 @@ hipError_t launch_get_populations(const LatDesc &d, int src, double *f, hipStrea
 int moments_blocks(int64_t n)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
-    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+    return (int)(b < kMomentsMaxBlocks ? (b < 1 ? 1 : b) : kMomentsMaxBlocks);
 }
 
 hipError_t launch_moments(const LatDesc &d, int src, double *rho, double *ux, double *uy,
@@ -428,9 +430,10 @@ hipError_t launch_moments(const LatDesc &d, int src, double *rho, double *ux, do
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s)
+hipError_t launch_reduce(const double *partials, int nblocks, int ncomp, double *out, hipStream_t s,
+                         double base0)
 {
-    k_reduce<<<1, kBlock, 0, s>>>(partials, nblocks, ncomp, out);
+    k_reduce<<<1, kBlock, 0, s>>>(partials, nblocks, ncomp, out, base0);
     return hipGetLastError();
 }
 
