@@ -387,18 +387,9 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.bc_y = cfg->bc_y;
     d.storage = cfg->storage;
     d.force_mode = clbm::FM_CONST;
-    // Premnath et al.'s scheme (Sec. III A) is Eq. (12) without the
-    // third-order force moments: the consistent kernel with their weight
-    // (1 - s3/2) zero.
-    d.scheme = cfg->scheme == CLBM_SCHEME_GUO_LBL ? clbm::SCH_GUO_LBL : clbm::SCH_CONSISTENT;
     d.rho0 = cfg->rho0;
-    d.om1 = 1.0 - cfg->s1;
-    d.omb = 1.0 - cfg->sb;
-    d.om2 = 1.0 - cfg->s2;
-    d.om3 = 1.0 - cfg->s3;
-    d.om4 = 1.0 - cfg->s4;
-    d.h3 = cfg->scheme == CLBM_SCHEME_PREMNATH ? 0.0 : 1.0 - 0.5 * cfg->s3;
-    d.h2 = 1.0 - 0.5 * cfg->s2;
+    static_assert(CLBM_SCHEME_GUO_LBL == 1 && CLBM_SCHEME_PREMNATH == 2, "set_rates' scheme numbers");
+    clbm::set_rates(d, cfg->s1, cfg->sb, cfg->s2, cfg->s3, cfg->s4, cfg->scheme);
     h->vec = default_vec(cfg->storage);
     h->occ = default_occupancy(cfg->storage, 2 * need, inplace, 1);
     h->lds = lds_for_occupancy(h->occ);

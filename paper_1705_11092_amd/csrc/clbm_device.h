@@ -47,7 +47,7 @@ static_assert(opp_of(5) == 7 && opp_of(6) == 8 && opp_of(7) == 5 && opp_of(8) ==
 
 // Rest weights w_i = f_i^eq(rho = 1, u = 0).
 template <typename R>
-__device__ __forceinline__ R weight(int i)
+__host__ __device__ __forceinline__ R weight(int i)
 {
     return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
 }
@@ -74,12 +74,25 @@ template <> struct Storage<ST_F32> {
     static __device__ __forceinline__ T from_r(R v) { return v; }
 };
 
+// The FP32 value v as computed, opaque to the optimiser.  gfx950 can fuse a
+// multiply-add and the conversion of its result to binary16 into one
+// instruction (v_fma_mixlo_f16) that rounds once, to 16 bits, instead of
+// twice; the compiler does so in some kernels and not in others, which would
+// then store different bits for the same node update.  Passing the FP32
+// result through an empty asm statement keeps the conversion a separate
+// instruction everywhere, at no cost in instructions.
+__device__ __forceinline__ float fp32_value(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 template <> struct Storage<ST_F16> {
     using T = _Float16;
     using R = float;
     static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
-    static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }  // RNE
+    static __device__ __forceinline__ T from_r(R v) { return (_Float16)fp32_value(v); }  // RNE
 };
 
 // bfloat16: gfx950 converts FP32 to bfloat16 in hardware, rounding to
@@ -89,7 +102,7 @@ template <> struct Storage<ST_BF16> {
     using R = float;
     static constexpr bool kDither = false;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
-    static __device__ __forceinline__ T from_r(R v) { return (__bf16)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (__bf16)fp32_value(v); }
 };
 
 // Stochastically rounded 16-bit storage.  A value that changes by a few
@@ -114,7 +127,7 @@ template <> struct Storage<ST_F16_SR> {
     using R = float;
     static constexpr bool kDither = true;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
-    static __device__ __forceinline__ T from_r(R v) { return (_Float16)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (_Float16)fp32_value(v); }
     static __device__ __forceinline__ T from_r_sr(R v, uint32_t rnd)
     {
         return __builtin_amdgcn_cvt_sr_f16_f32(half2_t{}, v, rnd, false)[0];
@@ -132,7 +145,7 @@ template <> struct Storage<ST_BF16_SR> {
     using R = float;
     static constexpr bool kDither = true;
     static __device__ __forceinline__ R to_r(T v) { return (float)v; }
-    static __device__ __forceinline__ T from_r(R v) { return (__bf16)v; }
+    static __device__ __forceinline__ T from_r(R v) { return (__bf16)fp32_value(v); }
     static __device__ __forceinline__ T from_r_sr(R v, uint32_t rnd)
     {
         return __builtin_amdgcn_cvt_sr_bf16_f32(bfloat2_t{}, v, rnd, false)[0];
@@ -172,16 +185,15 @@ enum SchemeKind { SCH_CONSISTENT = 0, SCH_GUO_LBL = 1 };
 
 template <typename R>
 struct Rates {
-    R om1;   // 1 - s1
-    R omb;   // 1 - sb
-    R om2;   // 1 - s2
-    R om3;   // 1 - s3
-    R om4;   // 1 - s4
-    R h3;    // 1 - s3/2 (force weight on the third-order slots, Eq. 12);
-             // 0 for the scheme of Sec. III A, whose force moments (Eq. 19)
-             // stop at first order
-    R h2;    // 1 - s2/2 (force weight of Eq. 21)
-    R rho0;
+    R nap, nam;       // -(sb + s2)/2, -(sb - s2)/2: k~20, k~02 relax as a trace
+                      // at sb and a deviator at s2 (Eq. 12)
+    R ns2, ns3, ns4;  // -s2, -s3, -s4
+    R h3t;            // (1 - s3/2) cs^2: third-order force weight of Eq. (12);
+                      // 0 for the scheme of Sec. III A, whose force moments
+                      // (Eq. 19) stop at first order
+    R g1;             // s1/2 + 1 - s2/2: first-order change per unit force (Eq. 21)
+    R h2;             // 1 - s2/2 (force weight of Eq. 21)
+    R rho0, r3;       // rho0 and rho0/3
 };
 
 // ---- the node update -------------------------------------------------------
@@ -240,34 +252,48 @@ __host__ __device__ __forceinline__ void from_central(R dr, R rho, R mx, R my, R
     g[8] = qr * (-r11 - r21 + r12 + r22);
 }
 
-// Change of the raw-moment deviations and populations for a change D of the
-// central moments about u (Eq. 9 applied to D, D0 = 0):
+// g += M^-1 N^-1(u) D for a change D of the central moments about u
+// (Eq. 9 applied to the change, D0 = 0):
 //   d10, d01 : D k~10, D k~01
 //   d20, d02 : D k~20, D k~02
 //   d11..d22 : D k~11, D k~21, D k~12, D k~22
-// dg receives M^-1 N^-1(u) D.
+// N^-1(u) is the binomial shift of the moments by u; it factorises into a
+// shift along x (k_mn -> k_mn + m ux k_(m-1)n + ...) followed by one along
+// y, which is how it is applied here (14 multiply-adds instead of the 28 of
+// the expanded rows).  M^-1 (Appendix) is then taken on sums and
+// differences of the raw moments, each population's half or quarter folded
+// into its update.
 template <typename R>
-__host__ __device__ __forceinline__ void delta_back(R ux, R uy, R d10, R d01, R d20, R d02, R d11,
-                                                    R d21, R d12, R d22, R dg[9])
+__host__ __device__ __forceinline__ void add_back(R g[9], R ux, R uy, R d10, R d01, R d20, R d02, R d11,
+                                                  R d21, R d12, R d22)
 {
-    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
-    const R r20 = d20 + R(2) * ux * d10;
-    const R r02 = d02 + R(2) * uy * d01;
-    const R r11 = d11 + ux * d01 + uy * d10;
-    const R r21 = d21 + R(2) * ux * d11 + uy * d20 + uxx * d01 + R(2) * uxy * d10;
-    const R r12 = d12 + R(2) * uy * d11 + ux * d02 + uyy * d10 + R(2) * uxy * d01;
-    const R r22 = d22 + R(2) * ux * d12 + R(2) * uy * d21 + uxx * d02 + uyy * d20 + R(4) * uxy * d11 +
-                  R(2) * ux * uyy * d10 + R(2) * uxx * uy * d01;
+    const R ux2 = ux + ux, uy2 = uy + uy, uxx = ux * ux, uyy = uy * uy;
+    // Shift along x (the moments of order 0 in x are unchanged).
+    const R t20 = d20 + ux2 * d10;
+    const R t11 = d11 + ux * d01;
+    const R t21 = d21 + ux2 * d11 + uxx * d01;
+    const R t12 = d12 + ux * d02;
+    const R t22 = d22 + ux2 * d12 + uxx * d02;
+    // Shift along y: the raw moments r_mn (r10 = d10, r01 = d01, r20 = t20).
+    const R r02 = d02 + uy2 * d01;
+    const R r11 = t11 + uy * d10;
+    const R r21 = t21 + uy * t20;
+    const R r12 = t12 + uy2 * t11 + uyy * d10;
+    const R r22 = t22 + uy2 * t21 + uyy * t20;
+    // M^-1, row by row.
     const R h = R(0.5), qr = R(0.25);
-    dg[0] = r22 - (r20 + r02);
-    dg[1] = h * (d10 + r20 - r12 - r22);
-    dg[2] = h * (d01 + r02 - r21 - r22);
-    dg[3] = h * (-d10 + r20 + r12 - r22);
-    dg[4] = h * (-d01 + r02 + r21 - r22);
-    dg[5] = qr * (r11 + r21 + r12 + r22);
-    dg[6] = qr * (-r11 + r21 - r12 + r22);
-    dg[7] = qr * (r11 - r21 - r12 + r22);
-    dg[8] = qr * (-r11 - r21 + r12 + r22);
+    const R a = t20 - r22, b = d10 - r12;
+    const R c = r02 - r22, e = d01 - r21;
+    const R p = r22 + r11, q = r22 - r11, m = r21 + r12, n = r21 - r12;
+    g[0] = g[0] + (r22 - (t20 + r02));
+    g[1] = g[1] + h * (a + b);
+    g[3] = g[3] + h * (a - b);
+    g[2] = g[2] + h * (c + e);
+    g[4] = g[4] + h * (c - e);
+    g[5] = g[5] + qr * (p + m);
+    g[7] = g[7] + qr * (p - m);
+    g[6] = g[6] + qr * (q + n);
+    g[8] = g[8] + qr * (q - n);
 }
 
 // One collision in place: g holds pre-collision deviations on entry and
@@ -279,71 +305,76 @@ __host__ __device__ __forceinline__ void collide(R g[9], R Fx, R Fy, const Rates
     const R ninth = R(1) / R(9);
     const R h = R(0.5);
 
-    // Eq. (11) on deviations, Eq. (15).
+    // Eq. (11) on deviations, and the raw moments of g (Eq. 2).  (Regrouping
+    // these sums so that jx shares kxyy's rounding, or dr kxx's, saves a few
+    // adds but made the FP32 drift of slow steady flows several times worse:
+    // a 124^2 Kolmogorov flow at tau 1.36 went from 3e-6 to 1.4e-5 relative
+    // after 40,000 steps in a host emulation of the kernel.)
     const R sx = g[1] + g[3];
     const R sy = g[2] + g[4];
-    const R sd = (g[5] + g[6]) + (g[7] + g[8]);
-    const R dr = g[0] + sx + sy + sd;
+    const R kxxyy = (g[5] + g[6]) + (g[7] + g[8]);
+    const R dr = g[0] + sx + sy + kxxyy;
     const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    const R rho = rt.rho0 + dr;
-    const R inv = recip(rho);
-    const R mx = jx + h * Fx;  // rho ux (Eq. 15)
-    const R my = jy + h * Fy;
-    const R ux = mx * inv;
-    const R uy = my * inv;
-
-    // Raw moments of g above first order.
-    const R kxx = sx + sd;
-    const R kyy = sy + sd;
+    const R kxx = sx + kxxyy;
+    const R kyy = sy + kxxyy;
     const R kxy = (g[5] + g[7]) - (g[6] + g[8]);
     const R kxxy = (g[5] + g[6]) - (g[7] + g[8]);
     const R kxyy = (g[5] + g[8]) - (g[6] + g[7]);
-    const R kxxyy = sd;
-
-    // Central moments as deviations from T~eq (Eq. 8).
+    const R rho = rt.rho0 + dr;
+    const R inv = recip(rho);
+    const R hFx = h * Fx, hFy = h * Fy;
+    const R mx = jx + hFx;  // rho ux (Eq. 15)
+    const R my = jy + hFy;
+    const R ux = mx * inv;
+    const R uy = my * inv;
     const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
-    const R r3 = rt.rho0 * third;
-    const R cxx = kxx - dr * third - mx * ux + ux * Fx;
-    const R cyy = kyy - dr * third - my * uy + uy * Fy;
-    const R cxy = kxy - mx * uy + h * (ux * Fy + uy * Fx);
-    const R cxxy = kxxy - R(2) * ux * kxy - uy * (kxx + r3) + R(2) * mx * uxy - h * uxx * Fy -
-                   uxy * Fx;
-    const R cxyy = kxyy - R(2) * uy * kxy - ux * (kyy + r3) + R(2) * my * uxy - h * uyy * Fx -
-                   uxy * Fy;
-    const R cxxyy = kxxyy - dr * ninth - R(2) * ux * kxyy - R(2) * uy * kxxy + uxx * kyy + uyy * kxx +
-                    (uxx + uyy) * r3 + R(4) * uxy * kxy - R(3) * mx * ux * uyy +
-                    uxy * (uy * Fx + ux * Fy);
+    const R ux2 = ux + ux, uy2 = uy + uy;
+
+    // Central moments (Eq. 6) as deviations from T~eq (Eq. 8).  With
+    // j = rho u - F/2 the shift of the raw moments simplifies to
+    //   k~11         = kxy - uy jx + ux Fy/2
+    //   k~20 - rho/3 = kxx - dr/3 - ux (jx - Fx/2)
+    //   k~21         = kxxy - uy (kxx + rho0/3) - 2 ux k~11 + ux^2 Fy/2
+    //   k~22 - rho/9 = kxxyy - dr/9 - 2 uy k~21 - 2 ux k~12 - uy^2 k~20
+    //                  - ux^2 k~02 - 4 ux uy k~11 + ux uy (uy Fx + ux Fy)
+    //                  - rho ux^2 uy^2
+    // (the last from the expansion of sum f ex^2 ey^2 about u, with
+    // k~10 = -Fx/2 and k~01 = -Fy/2), and their x <-> y images.
+    const R cxy = kxy - uy * jx + ux * hFy;
+    const R cxx = kxx - dr * third - ux * (jx - hFx);
+    const R cyy = kyy - dr * third - uy * (jy - hFy);
+    const R cxxy = kxxy - uy * (kxx + rt.r3) - ux2 * cxy + uxx * hFy;
+    const R cxyy = kxyy - ux * (kyy + rt.r3) - uy2 * cxy + uyy * hFx;
+    const R rho3 = rho * third;
+    const R cxxyy = kxxyy - dr * ninth - uy2 * cxxy - ux2 * cxyy - uyy * (cxx + rho3) - uxx * (cyy + rho3) -
+                    uxy * (R(4) * cxy + (uxy * rho - (uy * Fx + ux * Fy)));
 
     // Change of each central moment, Eq. (12) (or Eq. 21): the relaxation
-    // -s (T~ - T~eq) = (1 - s - 1) (...) and the force term.
-    const R D3 = (rt.omb - R(1)) * (cxx + cyy);
-    const R D4 = (rt.om2 - R(1)) * (cxx - cyy);
-    const R D5 = (rt.om2 - R(1)) * cxy;
-    R D6 = (rt.om3 - R(1)) * cxxy;
-    R D7 = (rt.om3 - R(1)) * cxyy;
-    R D8 = (rt.om4 - R(1)) * cxxyy;
-    R D1, D2;
+    // -s (T~ - T~eq) and the force term; k~20 and k~02 relax as a trace
+    // at sb and a deviator at s2.
+    const R d20 = rt.nap * cxx + rt.nam * cyy;
+    const R d02 = rt.nam * cxx + rt.nap * cyy;
+    const R d11 = rt.ns2 * cxy;
+    R d21, d12, d22, d10, d01;
     if (SCH == SCH_CONSISTENT) {
         // Eq. (14): C = [0, Fx, Fy, 0, 0, 0, Fy/3, Fx/3, 0].  The first-order
         // central moments go from -F/2 to +F/2 whatever s1 is.
-        D1 = Fx;
-        D2 = Fy;
-        D6 += rt.h3 * (third * Fy);
-        D7 += rt.h3 * (third * Fx);
+        d10 = Fx;
+        d01 = Fy;
+        d21 = rt.ns3 * cxxy + rt.h3t * Fy;
+        d12 = rt.ns3 * cxyy + rt.h3t * Fx;
+        d22 = rt.ns4 * cxxyy;
     } else {
         // Eq. (21): central moments of Guo's term, weighted by 1 - s2/2; the
         // first-order slots relax at s1 from -F/2.
-        D1 = h * (R(1) - rt.om1) * Fx + rt.h2 * Fx;
-        D2 = h * (R(1) - rt.om1) * Fy + rt.h2 * Fy;
-        D6 += rt.h2 * (third * Fy - R(2) * uxy * Fx - uxx * Fy);
-        D7 += rt.h2 * (third * Fx - uyy * Fx - R(2) * uxy * Fy);
-        D8 += rt.h2 * (R(4) * uxy * (uy * Fx + ux * Fy));
+        d10 = rt.g1 * Fx;
+        d01 = rt.g1 * Fy;
+        d21 = rt.ns3 * cxxy + rt.h2 * (third * Fy - R(2) * uxy * Fx - uxx * Fy);
+        d12 = rt.ns3 * cxyy + rt.h2 * (third * Fx - uyy * Fx - R(2) * uxy * Fy);
+        d22 = rt.ns4 * cxxyy + rt.h2 * (R(4) * uxy * (uy * Fx + ux * Fy));
     }
-    R dg[9];
-    delta_back<R>(ux, uy, D1, D2, h * (D3 + D4), h * (D3 - D4), D5, D6, D7, D8, dg);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] += dg[i];
+    add_back<R>(g, ux, uy, d10, d01, d20, d02, d11, d21, d12, d22);
 }
 
 // Pre-collision deviations of the start state (central moments

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "clbm_device.h"
+
 namespace clbm {
 
 // Where the force density of a lattice comes from.
@@ -71,8 +73,33 @@ struct LatDesc {
     double Fx, Fy;       // FM_CONST force density
     double sc_g, sc_psi0, sc_rho;  // FM_SC: G, psi0 and rho_ref of psi = psi0 exp(-rho_ref/rho)
     double rho0;
-    double om1, omb, om2, om3, om4, h3, h2;  // 1 - s and force weights
+    // Relaxation and force weights of the collision (set_rates).
+    double nap, nam;       // -(sb + s2)/2, -(sb - s2)/2
+    double ns2, ns3, ns4;  // -s2, -s3, -s4
+    double h3t;            // (1 - s3/2) cs^2, or 0 (Sec. III A)
+    double g1;             // s1/2 + 1 - s2/2 (Eq. 21)
+    double h2;             // 1 - s2/2 (Eq. 21)
 };
+
+// The collision's constants for S = diag(s0, s1, s1, sb, s2, s2, s3, s3, s4)
+// (Sec. II A) and a forcing scheme (0: Eq. 12, 1: Eq. 21, 2: Premnath et
+// al.'s, Eqs. 17-19), in double precision.  The second-order central
+// moments relax as a trace at sb and a deviator at s2, so the changes of
+// k~20 and k~02 are nap c20 + nam c02 and nam c20 + nap c02 (c = departure
+// from equilibrium).  The scheme of Sec. III A is Eq. (12) without the
+// third-order force moments: the same kernel with h3t = 0.
+inline void set_rates(LatDesc &d, double s1, double sb, double s2, double s3, double s4, int scheme)
+{
+    d.scheme = scheme == 1 ? SCH_GUO_LBL : SCH_CONSISTENT;
+    d.nap = -0.5 * (sb + s2);
+    d.nam = -0.5 * (sb - s2);
+    d.ns2 = -s2;
+    d.ns3 = -s3;
+    d.ns4 = -s4;
+    d.h3t = scheme == 2 ? 0.0 : (1.0 - 0.5 * s3) / 3.0;
+    d.g1 = 0.5 * s1 + 1.0 - 0.5 * s2;
+    d.h2 = 1.0 - 0.5 * s2;
+}
 
 // Lattice descriptors carried in one upload kernel's arguments.
 constexpr int kUploadMax = 12;

@@ -21,17 +21,19 @@ namespace clbm {
 namespace {
 
 template <typename R>
-__device__ __forceinline__ Rates<R> rates_of(const LatDesc &d)
+__host__ __device__ __forceinline__ Rates<R> rates_of(const LatDesc &d)
 {
     Rates<R> rt;
-    rt.om1 = R(d.om1);
-    rt.omb = R(d.omb);
-    rt.om2 = R(d.om2);
-    rt.om3 = R(d.om3);
-    rt.om4 = R(d.om4);
-    rt.h3 = R(d.h3);
+    rt.nap = R(d.nap);
+    rt.nam = R(d.nam);
+    rt.ns2 = R(d.ns2);
+    rt.ns3 = R(d.ns3);
+    rt.ns4 = R(d.ns4);
+    rt.h3t = R(d.h3t);
+    rt.g1 = R(d.g1);
     rt.h2 = R(d.h2);
     rt.rho0 = R(d.rho0);
+    rt.r3 = R(d.rho0 / 3.0);
     return rt;
 }
 
