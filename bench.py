@@ -23,7 +23,13 @@ reference for scaling the HBM byte counters of rocprofv3).
 `--traffic-summary FETCH_STEP WRITE_STEP FETCH_COPY WRITE_COPY` (CPU only)
 turns the counter_collection.csv files of the four rocprofv3 --pmc runs
 listed in the summary into profiles/traffic_step_f32_tg4096.json, stamped
-with the hash of the kernel sources they were taken on.
+with the hash of the kernel sources they were taken on;
+`--valu-summary PMC_DIR` does the same for one run of
+`--pmc SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE` (profiles/valu_step_f32_tg4096.json).
+The line's roofline names the binding limit of the headline kernel: HBM
+(algorithmic bytes per launch against 8 TB/s) or VALU issue (the counted
+wave-instructions per launch against 256 CUs x 2.4 GHz x one wave64
+instruction per clock), and carries both.
 """
 from __future__ import annotations
 
@@ -48,6 +54,9 @@ KERNEL_SOURCES = ["paper_1705_11092_amd/csrc/clbm_step_f32.hip",
                   "paper_1705_11092_amd/csrc/clbm_device.h",
                   "paper_1705_11092_amd/csrc/clbm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_tg4096.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_step_f32_tg4096.json")
+# VALU issue peak: 256 CUs x 2.4 GHz x one wave64 vector instruction per CU per clock.
+VALU_PEAK_G = 256 * 2.4
 
 
 def kernel_hash() -> str:
@@ -79,8 +88,29 @@ def measured_traffic(storage: str, n_nodes: int):
     return t.get("hbm_bytes_per_launch")
 
 
+def measured_valu(storage: str, n_nodes: int):
+    """VALU wave-instructions per launch of the two-step kernel from the
+    committed rocprofv3 counter summary, or None when the kernel sources
+    changed since it was taken."""
+    try:
+        with open(VALU_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("storage") != storage or t.get("nodes") != n_nodes:
+        return None
+    return t
+
+
 def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False,
-            pairs: bool = True):
+            pairs: bool = True, reps: int = 1):
+    """Time `reps` repetitions of exactly `steps` steps each (HIP events on
+    the lattice's stream, a device synchronisation on both sides of each)
+    after `warmup` untimed steps.  Returns the median repetition's
+    milliseconds, the wall time of all repetitions, the FP64 totals at the
+    end and the list of repetitions."""
+    import statistics
+
     import torch
     from paper_1705_11092_amd import clbm, inputs
 
@@ -93,17 +123,20 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int, inplace: bool = False
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    times = []
     wall0 = time.perf_counter()
-    t0.record(stream)
-    lat.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0.record(stream)
+        lat.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        times.append(t0.elapsed_time(t1))
     wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1)
     _, _, _, tot = lat.moments(fields=False)
     lat.close()
-    return ms, wall, tot
+    run_gpu.reps = times
+    return statistics.median(times), wall, tot
 
 
 def run_small():
@@ -183,8 +216,9 @@ def run_served(count: int):
     from paper_1705_11092_amd import inputs
     from paper_1705_11092_amd.serve import GpuBackend, Server
 
-    # Saturation: the same kind of stream with every request waiting at t = 0.
-    sat = inputs.served_stream(count=count, seed=2, rate=1e9)
+    # Saturation: the same kind of stream with every request waiting at t = 0
+    # (a throughput: 100 requests measure it well enough).
+    sat = inputs.served_stream(count=min(count, 100), seed=2, rate=1e9)
     rep = Server(GpuBackend()).run(sat)
     mu = rep.summary()["done"] / rep.makespan
     torch.cuda.empty_cache()
@@ -193,7 +227,8 @@ def run_served(count: int):
     s = rep.summary()
     torch.cuda.empty_cache()
     return {"workload": f"{count} solves, sides log-uniform 64..2048, steps log-uniform 1e3..1e5, "
-                        "forcing const/kolmogorov/none, f32 or f16 storage, Poisson arrivals",
+                        "forcing const/kolmogorov/none, f32 or f16 (stochastic rounding) storage, "
+                        "Poisson arrivals",
             "saturation_rps": round(mu, 3), "arrival_rps": round(0.8 * mu, 3),
             "p50_latency_s": round(s["p50_latency_s"], 4), "p99_latency_s": round(s["p99_latency_s"], 4),
             "mlups": round(s["mlups"], 1), "done": s["done"], "rejected": s["rejected"],
@@ -265,6 +300,46 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
                                            "fetch_scale", "write_scale", "kernel_hash")}))
 
 
+def valu_summary(d: str, n: int = 4096):
+    """VALU wave-instructions, waves and clock per launch of the two-step
+    kernel from one rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE run
+    (its run_counter_collection.csv), written to profiles/valu_step_f32_tg4096.json
+    with the hash of the kernel sources it was taken on."""
+    import csv
+    import statistics
+    step = "k_step2<1, 0, 0, unsigned int>"
+    per = {}
+    with open(os.path.join(d, "run_counter_collection.csv"), newline="") as fh:
+        for row in csv.DictReader(fh):
+            if step not in row["Kernel_Name"]:
+                continue
+            e = per.setdefault(row.get("Dispatch_Id") or row.get("Correlation_Id"), {})
+            e[row["Counter_Name"]] = float(row["Counter_Value"])
+            if row.get("Start_Timestamp") and row.get("End_Timestamp"):
+                e["ns"] = float(row["End_Timestamp"]) - float(row["Start_Timestamp"])
+    if not per:
+        raise SystemExit(f"{d}: no counter rows for {step}")
+    valu = statistics.median(e["SQ_INSTS_VALU"] for e in per.values())
+    waves = statistics.median(e["SQ_WAVES"] for e in per.values())
+    clocks = [e["GRBM_GUI_ACTIVE"] / 8.0 / e["ns"] for e in per.values() if e.get("ns")]
+    out = {
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int> (two fused steps per launch; FP32 deviations, constant "
+                  "force, consistent scheme)",
+        "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
+        "kernel_hash": kernel_hash(),
+        "command": f"rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE --output-format csv -d {d} -o run "
+                   "-- python3 bench.py --steps 6 --warmup 0 --no-cpu-baseline --no-extra",
+        "dispatches": len(per), "valu_wave_insts_per_launch": valu, "waves_per_launch": waves,
+        "valu_insts_per_wave": round(valu / waves, 1),
+        "valu_insts_per_node_update": round(valu * 64 / (2 * n * n), 1),
+        "issue_us_at_2p4_ghz": round(valu / (256 * 2.4e9) * 1e6, 2),
+        "clock_ghz": round(statistics.median(clocks), 3) if clocks else None,
+    }
+    with open(VALU_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0):
     """The oracle on the host cores: the same 4096^2 workload, as many steps
     as fit in about budget_s seconds after one timed probe step."""
@@ -298,14 +373,22 @@ def main():
                     help="only the main lattice (16-bit, batch and served legs skipped)")
     ap.add_argument("--single-steps", action="store_true",
                     help="step the main lattice one step per launch (no fused pairs)")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
     ap.add_argument("--traffic-summary", nargs=4, default=None,
                     metavar=("FETCH_STEP", "WRITE_STEP", "FETCH_COPY", "WRITE_COPY"))
+    ap.add_argument("--valu-summary", default=None, metavar="PMC_DIR")
+    ap.add_argument("--reps", type=int, default=0,
+                    help="timed repetitions of the headline (default: at least 5 and 400 steps)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 256-lattice batch leg (for profiling it)")
     args = ap.parse_args()
 
     if args.traffic_summary:
         traffic_summary(args.traffic_summary)
+        return
+    if args.valu_summary:
+        valu_summary(args.valu_summary)
         return
 
     if args.calibrate_copy:
@@ -318,7 +401,16 @@ def main():
               "exchange per step.", file=sys.stderr)
         sys.exit(2)
 
-    ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=not args.single_steps)
+    # The headline: reps repetitions of exactly K steps each, the median
+    # repetition reported (at least 5 repetitions and 400 timed steps).
+    reps = args.reps or max(5, -(-400 // max(args.steps, 1)))
+    if args.batch_only:
+        print(json.dumps(run_batch(max(args.steps, 2), args.warmup)), flush=True)
+        return
+
+    ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=not args.single_steps,
+                            reps=reps)
+    rep_ms = run_gpu.reps
     pairs = run_gpu.pairs
     nodes = args.n * args.n
     ms_step = ms / args.steps
@@ -330,6 +422,30 @@ def main():
     ms_launch = ms_step * steps_per_launch
     achieved = bpl * nodes / (ms_launch / 1e3) / 1e9
     traffic = measured_traffic(args.storage, nodes) if pairs else None
+    limits = {"hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                      "algorithmic_bytes_per_launch": bpl * nodes}}
+    valu = measured_valu(args.storage, nodes) if pairs else None
+    if valu is not None:
+        # VALU issue: a compute unit issues at most one wave64 vector
+        # instruction per clock (FP32 arithmetic unpacked), 256 CUs at 2.4 GHz.
+        per_s = valu["valu_wave_insts_per_launch"] / (ms_launch / 1e3) / 1e9
+        limits["alu"] = {"achieved": round(per_s, 1), "peak": VALU_PEAK_G, "unit": "G VALU wave-instr/s",
+                         "frac": round(per_s / VALU_PEAK_G, 4),
+                         "valu_wave_insts_per_launch": valu["valu_wave_insts_per_launch"],
+                         "clock_ghz_under_counters": valu.get("clock_ghz")}
+    bound = max(limits, key=lambda k: limits[k]["frac"])
+    roof = {"bound": bound, **{k: v for k, v in limits[bound].items()},
+            "kernel": "k_step2 (two fused steps per launch)" if pairs else "k_step",
+            "ms_per_launch": round(ms_launch, 5), "limits": limits}
+    if pairs:
+        # The per-update byte model (every node update reads and writes the
+        # state once) does not hold for fused pairs: the state crosses HBM
+        # once per two updates.
+        per_update = bpl * nodes * steps_per_launch / (ms_launch / 1e3) / 1e9
+        roof["per_update_model"] = {"bytes_per_update": bpl, "equivalent_gb_s": round(per_update, 1),
+                                    "frac_of_hbm_peak": round(per_update / HBM_PEAK_GBS, 4),
+                                    "note": "exceeds 1: the model assumes no reuse across steps"}
     line = {
         "metric": "MLUPS (D2Q9 CLBM step, consistent forcing)",
         "value": round(mlups, 1),
@@ -348,17 +464,15 @@ def main():
                    "nodes": nodes, "steps_per_launch": steps_per_launch,
                    "hbm_bytes_per_lup": bpl / steps_per_launch, "boundary": "periodic",
                    "u0": 0.01, "nu": 0.01, "F": [1e-6, 5e-7]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "k_step2 (two fused steps per launch)" if pairs else "k_step",
-                     "algorithmic_bytes_per_launch": bpl * nodes,
-                     "ms_per_launch": round(ms_launch, 5)},
+        "roofline": roof,
+        "timing": {"repetitions": reps, "steps_each": args.steps, "statistic": "median",
+                   "ms_per_repetition": [round(t, 4) for t in rep_ms]},
         "wall_s": round(wall, 4),
         "mass_total": tot[0],
     }
     if not args.no_extra:
         extra = {}
+        args.steps = max(args.steps, 200)  # the other legs: one repetition of at least 200 steps
         ms1, _, _ = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=False)
         m = nodes / (ms1 / args.steps / 1e3) / 1e6
         extra[f"{args.storage}_one_step_per_launch"] = {

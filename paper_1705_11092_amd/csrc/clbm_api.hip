@@ -715,8 +715,11 @@ double clbm_s_from_nu(double nu) { return 1.0 / (3.0 * nu + 0.5); }
 
 namespace {
 
-// Kernel variants of a batch: bytes each thread loads per direction (nodes
-// per thread = bytes / element size, clamped to the compiled set), the grid
+// Kernel variants of a batch.  A variant is a pair (single-step variant,
+// two-step variant): the first applies to the groups whose lattices step one
+// step per launch, the second to those that step in pairs.
+// Single-step variants: bytes each thread loads per direction (nodes per
+// thread = bytes / element size, clamped to the compiled set), the grid
 // (persistent blocks per compute unit, or 0: one block per tile) and a cap
 // on resident blocks per compute unit (0: none, -1: the single-lattice
 // default of the group's storage type for the group's traffic).
@@ -729,7 +732,21 @@ const Variant kVariants[] = {
     {16, 0, -1}, {16, 0, 0}, {16, 0, 4}, {16, 16, 0}, {8, 0, -1},
     {8, 0, 0},   {8, 16, 0}, {4, 0, -1}, {4, 0, 0},  {4, 16, 0},
 };
-constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kNumSingle = sizeof(kVariants) / sizeof(kVariants[0]);
+// Two-step variants: the tile shape (64 x 16 or 32 x 32 nodes) and the grid
+// (persistent blocks per compute unit walking the tiles, or 0: one block per
+// tile; the two-step kernel's LDS lets 4 blocks share a compute unit).
+struct PairVariant {
+    int shape;
+    int blocks_per_cu;
+};
+const PairVariant kPairVariants[] = {
+    {clbm::kTile64x16, 0}, {clbm::kTile32x32, 0}, {clbm::kTile64x16, 4}, {clbm::kTile32x32, 4}};
+constexpr int kNumPair = sizeof(kPairVariants) / sizeof(kPairVariants[0]);
+constexpr int kNumVariants = kNumSingle * kNumPair;
+int single_index(int v) { return v / kNumPair; }
+const Variant &single_of(int v) { return kVariants[v / kNumPair]; }
+const PairVariant &pair_of(int v) { return kPairVariants[v % kNumPair]; }
 
 int vec_for(int storage, int vec_bytes)
 {
@@ -808,15 +825,17 @@ void batch_geometry(clbm_batch *b)
         const int key = group_key(h0);
         const bool pairs = use_pairs(h0);
         const int st = d0.storage;
-        const int vec = pairs ? 4 : vec_for(st, kVariants[b->variant].vec_bytes);
+        const int vec = pairs ? 4 : vec_for(st, single_of(b->variant).vec_bytes);
+        const int shape = pair_of(b->variant).shape;
         const int lo = (int)pos;
         int64_t tiles = 0;
         size_t bytes = 0, largest = 0;
         while (pos < b->order.size() && group_key(b->lats[b->order[pos]]) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
             clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
-            if (pairs)  // tiles of the two-step kernel: 64 columns x 16 rows
-                d.ntiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + 15) / 16);
+            if (pairs)  // tiles of the two-step kernel in the variant's shape
+                d.ntiles = (int64_t)((d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape)) *
+                           ((d.ny + clbm::tile_h(shape) - 1) / clbm::tile_h(shape));
             d.vec = vec;
             d.pairs = pairs ? 1 : 0;
             d.tile0 = tiles;
@@ -827,7 +846,7 @@ void batch_geometry(clbm_batch *b)
             b->tab[pos] = d;
             ++pos;
         }
-        const int cap = kVariants[b->variant].cap;
+        const int cap = single_of(b->variant).cap;
         const size_t lds = lds_for_occupancy(cap < 0 ? default_occupancy(st, bytes) : cap);
         const bool small = largest + 4096 < ((size_t)1 << 32);
         b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds, pairs, small});
@@ -915,16 +934,19 @@ int batch_side_streams(clbm_batch *b, size_t n)
     return CLBM_OK;
 }
 
-// Steps k0 .. k0 + n - 1 of the current call for every group.  The groups
+// Steps k0 .. k0 + n - 1 of the current call for every group (which = 3),
+// or only the groups that step singly (1) or in pairs (2).  The groups
 // touch disjoint lattices, so with more than one they run concurrently:
 // group 0 on s, the others on side streams forked from s once and joined
 // back to it after their n steps (a group of small lattices alone leaves
 // HBM idle in its tail; measured +15 % on a batch of FP32 and FP16
 // lattices).  Within a group the steps follow each other in stream order.
-int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s)
+int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s, int which = 3)
 {
-    const Variant &v = kVariants[b->variant];
+    const Variant &v = single_of(b->variant);
+    const PairVariant &pv = pair_of(b->variant);
     const int64_t grid = v.blocks_per_cu ? (int64_t)b->cus * v.blocks_per_cu : INT32_MAX;
+    const int64_t pgrid = pv.blocks_per_cu ? (int64_t)b->cus * pv.blocks_per_cu : 0;
     const size_t ng = b->groups.size();
     if (ng > 1) {
         int rc = batch_side_streams(b, ng - 1);
@@ -935,10 +957,13 @@ int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s)
     for (size_t k = 0; k < ng; ++k) {
         const auto &g = b->groups[k];
         hipStream_t gs = k == 0 ? s : b->side[k - 1];
+        if (!(which & (g.pairs ? 2 : 1))) continue;
         if (g.pairs) {
             // Steps k0 .. k0 + n - 1 as pair substeps (k0 is even).
+            const int gg = (int)std::min<int64_t>(pgrid, g.ntiles);
             for (int p = k0 / 2; p < (k0 + n + 1) / 2; ++p)
-                HIPCHK(clbm::launch_batch2(g.storage, b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key, g.small, p, gs));
+                HIPCHK(clbm::launch_batch2(g.storage, b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key,
+                                           g.small, p, pv.shape, gg, gs));
             continue;
         }
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
@@ -1026,7 +1051,7 @@ std::string batch_signature(const clbm_batch *b)
         counts[h->d.storage] += 1;
     }
     std::ostringstream os;
-    os << arch;
+    os << arch << "|v" << kNumSingle << "x" << kNumPair;
     for (int st = 0; st < kStorageKinds; ++st) {
         // Shape class: lattice count and log2 of the node total per storage.
         int lg = 0;
@@ -1124,13 +1149,23 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
             }
         }
     }
-    // Time one step of every lattice per variant.  The timed launches read
-    // the current state and write the other buffer without advancing the
-    // lattices, so the state is untouched (the next real step overwrites
-    // that buffer).  In-place lattices have no other buffer: their timed
-    // launches write one scratch allocation as large as the largest of
-    // them (all into the same place; its contents are never read).
-    std::vector<int64_t> ones(b->lats.size(), 1);
+    // Time the variants on the batch's own lattices: one step of every
+    // lattice that steps singly and one fused pair of every lattice that
+    // steps in pairs.  The timed launches read the current state and write
+    // the other buffer without advancing the lattices, so the state is
+    // untouched (the next real step overwrites that buffer).  In-place
+    // lattices have no other buffer: their timed launches write one scratch
+    // allocation as large as the largest of them (all into the same place;
+    // its contents are never read).  The single-step part of the variant is
+    // chosen first, on the groups that step singly, then the two-step part
+    // on the groups that step in pairs.
+    std::vector<int64_t> counts(b->lats.size(), 1);
+    bool any_single = false, any_pairs = false;
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+        const bool p = use_pairs(b->lats[j]);
+        counts[j] = p ? 2 : 1;
+        (p ? any_pairs : any_single) = true;
+    }
     size_t spare_bytes = 0;
     for (auto *h : b->lats)
         if (h->d.inplace)
@@ -1140,32 +1175,48 @@ int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen)
     hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
-    int best = b->variant;
-    float best_ms = 1e30f;
     int rc = CLBM_OK;
-    for (int v = 0; v < kNumVariants && rc == CLBM_OK; ++v) {
-        if ((rc = clbm_batch_set_variant(b, v))) break;
-        if ((rc = batch_upload(b, ones.data(), spare))) break;
+    // Mean time of one launch sequence of variant v over the groups `which`.
+    auto time_variant = [&](int v, int which, float *ms) -> int {
+        int r = clbm_batch_set_variant(b, v);
+        if (!r) r = batch_upload(b, counts.data(), spare);
         const int reps = 5;
-        for (int w = 0; w < 2 && rc == CLBM_OK; ++w) rc = batch_launch_steps(b, 0, 1, b->stream);
-        if (rc) break;
+        for (int w = 0; w < 2 && r == CLBM_OK; ++w) r = batch_launch_steps(b, 0, 1, b->stream, which);
+        if (r) return r;
         hipError_t e = hipEventRecord(t0, b->stream);
-        for (int r = 0; r < reps && rc == CLBM_OK && e == hipSuccess; ++r)
-            rc = batch_launch_steps(b, 0, 1, b->stream);
-        if (rc) break;
+        for (int k = 0; k < reps && r == CLBM_OK && e == hipSuccess; ++k)
+            r = batch_launch_steps(b, 0, 1, b->stream, which);
+        if (r) return r;
         if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "autotune events");
-            break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, t0, t1);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = v;
+        if (e != hipSuccess) return hip_fail(e, "autotune events");
+        (void)hipEventElapsedTime(ms, t0, t1);
+        return CLBM_OK;
+    };
+    int best_single = single_index(b->variant), best_pair = b->variant % kNumPair;
+    if (any_single) {
+        float best_ms = 1e30f;
+        for (int vs = 0; vs < kNumSingle && rc == CLBM_OK; ++vs) {
+            float ms = 0.f;
+            if ((rc = time_variant(vs * kNumPair + best_pair, 1, &ms))) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_single = vs;
+            }
         }
     }
+    if (any_pairs && rc == CLBM_OK) {
+        float best_ms = 1e30f;
+        for (int vp = 0; vp < kNumPair && rc == CLBM_OK; ++vp) {
+            float ms = 0.f;
+            if ((rc = time_variant(best_single * kNumPair + vp, 2, &ms))) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_pair = vp;
+            }
+        }
+    }
+    const int best = best_single * kNumPair + best_pair;
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (spare) (void)hipFreeAsync(spare, b->stream);

@@ -101,6 +101,12 @@ inline void set_rates(LatDesc &d, double s1, double sb, double s2, double s3, do
     d.h2 = 1.0 - 0.5 * s2;
 }
 
+// Tile shapes of the two-step kernels (columns x rows of nodes per block of
+// kBlock threads, 4 nodes per thread in its second step).
+enum TileShape { kTile64x16 = 0, kTile32x32 = 1 };
+inline int tile_w(int shape) { return shape == kTile32x32 ? 32 : 64; }
+inline int tile_h(int shape) { return shape == kTile32x32 ? 32 : 16; }
+
 // Lattice descriptors carried in one upload kernel's arguments.
 constexpr int kUploadMax = 12;
 struct UploadPayload {
@@ -154,13 +160,16 @@ hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s);
 // Pair substep `pair` of a batch group whose lattices step in pairs: each
 // lattice with at least 2 pair + 2 steps left takes two fused steps, one
 // with 2 pair + 1 left takes its last single step.  small: every buffer of
-// the group is below 4 GB; storage is the group's.
+// the group is below 4 GB; storage is the group's; shape the tile shape
+// (kTile64x16 or kTile32x32 of clbm_step2.h, which numbered the lattices'
+// tiles); grid 0 launches one block per tile, grid > 0 that many persistent
+// blocks walking the tiles.
 hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
-                         bool small, int pair, hipStream_t s);
+                         bool small, int pair, int shape, int grid, hipStream_t s);
 // The same per storage type, one translation unit each (clbm_step_*.hip).
 template <int ST>
 hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
-                            bool small, int pair, hipStream_t s);
+                            bool small, int pair, int shape, int grid, hipStream_t s);
 template <int ST>
 hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s);
 template <int ST>

@@ -312,17 +312,19 @@ hipError_t launch_step2(const LatDesc &d, int src, hipStream_t s)
 }
 
 hipError_t launch_batch2(int storage, const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key,
-                         bool small, int pair, hipStream_t s)
+                         bool small, int pair, int shape, int grid, hipStream_t s)
 {
+#define CLBM_B2(ST) launch_batch2_st<ST>(lats, tile_lat, ntiles, key, small, pair, shape, grid, s)
     switch (storage) {
-    case ST_F64: return launch_batch2_st<ST_F64>(lats, tile_lat, ntiles, key, small, pair, s);
-    case ST_F32: return launch_batch2_st<ST_F32>(lats, tile_lat, ntiles, key, small, pair, s);
-    case ST_F16: return launch_batch2_st<ST_F16>(lats, tile_lat, ntiles, key, small, pair, s);
-    case ST_BF16: return launch_batch2_st<ST_BF16>(lats, tile_lat, ntiles, key, small, pair, s);
-    case ST_F16_SR: return launch_batch2_st<ST_F16_SR>(lats, tile_lat, ntiles, key, small, pair, s);
-    case ST_BF16_SR: return launch_batch2_st<ST_BF16_SR>(lats, tile_lat, ntiles, key, small, pair, s);
+    case ST_F64: return CLBM_B2(ST_F64);
+    case ST_F32: return CLBM_B2(ST_F32);
+    case ST_F16: return CLBM_B2(ST_F16);
+    case ST_BF16: return CLBM_B2(ST_BF16);
+    case ST_F16_SR: return CLBM_B2(ST_F16_SR);
+    case ST_BF16_SR: return CLBM_B2(ST_BF16_SR);
     default: return hipErrorInvalidValue;
     }
+#undef CLBM_B2
 }
 
 hipError_t launch_resident(const LatDesc &d, int src, int nsteps, hipStream_t s)

@@ -2,17 +2,18 @@
 // (pull) form.  Included by the translation units of the storage types that
 // use it, after clbm_step.h.
 //
-// One block owns a tile of kTH rows x kTW columns.  Phase A collides step
-// n + 1 on the tile and a one-node halo around it (the nodes whose
-// post-collision values step n + 2 of the tile pulls, Eq. 10), reading the
-// state of step n from HBM, and keeps the results in LDS, rounded to the
-// storage type exactly as the one-step kernel would store them.  Phase B
-// collides step n + 2 on the tile from LDS and writes the other buffer.
-// The state thus crosses HBM once per two steps (plus the halo's re-reads),
-// and every node update is the one-step kernel's, so the result is bitwise
-// that of two one-step launches.
+// One block owns a tile of TH rows x TW columns (64 x 16 or 32 x 32, 256
+// threads, 4 nodes per thread in phase B).  Phase A collides step n + 1 on
+// the tile's region: the tile's nodes that lie in the lattice and a one-node
+// halo around them (the nodes whose post-collision values step n + 2 of the
+// tile pulls, Eq. 10), reading the state of step n from HBM, and keeps the
+// results in LDS, rounded to the storage type exactly as the one-step kernel
+// would store them.  Phase B collides step n + 2 on the tile from LDS and
+// writes the other buffer.  The state thus crosses HBM once per two steps
+// (plus the halo's re-reads), and every node update is the one-step
+// kernel's, so the result is bitwise that of two one-step launches.
 //
-// LDS holds, per slot i, the kTH x kTW values that the tile's nodes pull in
+// LDS holds, per slot i, the TH x TW values that the tile's nodes pull in
 // slot i (Eq. 10): entry [i][r][c] is what tile node (r, c) reads, the
 // post-collision slot i of node (r - e_y,i, c - e_x,i), or, where that node
 // lies beyond a wall, the node's own post-collision slot opp(i) (half-way
@@ -25,11 +26,21 @@
 #include "clbm_step.h"
 
 namespace clbm {
+
 namespace {
 
-constexpr int kTW = 64, kTH = 16;            // tile: columns x rows (4 nodes per thread in phase B)
-constexpr int kRW = kTW + 2, kRH = kTH + 2;  // the tile with its one-node halo
-constexpr int kStripTiles = 8;               // tile columns per strip of the tile walk
+template <int TW_, int TH_>
+struct Tile {
+    static constexpr int TW = TW_, TH = TH_;           // tile: columns x rows
+    static constexpr int RW = TW + 2, RH = TH + 2;     // the tile with its one-node halo
+    static constexpr int LPR = TW / 4;                 // phase-B threads per tile row
+    static_assert(TW * TH == 4 * kBlock, "phase B: 4 nodes per thread");
+    static_assert(RH <= 64 && 64 + RW <= kBlock, "table fill: rows by wave 0, columns from thread 64");
+};
+using T64x16 = Tile<64, 16>;
+using T32x32 = Tile<32, 32>;
+
+constexpr int kStripTiles = 8;  // tile columns per strip of the tile walk
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {
@@ -52,10 +63,10 @@ struct alignas(16) ColEnt {
     I om, o0, op;  // columns x - 1, x, x + 1 (periodic)
     int32_t x;
 };
-template <typename I>
+template <typename I, typename TL>
 struct TileTabs {
-    RowEnt<I> row[kRH];
-    ColEnt<I> col[kRW];
+    RowEnt<I> row[TL::RH];
+    ColEnt<I> col[TL::RW];
 };
 
 // Element e of a buffer.  I = uint32_t (buffers below 4 GB): a 32-bit byte
@@ -91,32 +102,48 @@ __device__ __forceinline__ I row_at(const LatDesc &d, int y)
 }
 
 // Two fused steps of the tile at (x0, y0) from buffer src into src ^ 1.
-template <int ST, int FM, int SCH, typename I>
+template <int ST, int FM, int SCH, typename I, typename TL>
 __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int y0,
-                                          typename Storage<ST>::T (&lds)[9][kTH][kTW], TileTabs<I> &tab)
+                                          typename Storage<ST>::T (&lds)[9][TL::TH][TL::TW],
+                                          TileTabs<I, TL> &tab)
 {
     using S = Storage<ST>;
     using T = typename S::T;
     using R = typename S::R;
+    constexpr int TW = TL::TW, TH = TL::TH;
     const T *in = static_cast<const T *>(d.buf[src]);
     T *out = static_cast<T *>(d.buf[src ^ 1]);
     const Rates<R> rt = rates_of<R>(d);
 
-    // Phase A: step n + 1 on the region, the tile and its one-node halo.
-    // The loads are ordinary, not non-temporal: the halo's lines are the
+    // Phase A: step n + 1 on the region: the tile's columns and rows that
+    // lie in the lattice, and one node around them (rw x rh nodes; a tile at
+    // the lattice's right or lower edge has a narrower or lower region, so
+    // small and ragged lattices collide only what phase B pulls).  The
+    // loads are ordinary, not non-temporal: the halo's lines are the
     // neighbouring tiles' own, read again a few tiles later, and the L2
     // keeps them only if they were not fetched with the streaming policy
     // (with non-temporal loads the fetched bytes were 1.31 times the state
     // read, with ordinary loads 1.04 times).
-    constexpr int kN = kRW * kRH, kPer = (kN + kBlock - 1) / kBlock;
+    constexpr int kN = TL::RW * TL::RH, kPer = (kN + kBlock - 1) / kBlock;
     constexpr I kU = sizeof(I) == 4 ? (I)sizeof(T) : (I)1;  // address units per element
+    const int rw = (d.nx - x0 < TW ? d.nx - x0 : TW) + 2;
+    const int rh = (d.ny - y0 < TH ? d.ny - y0 : TH) + 2;
+    const int nreg = rw * rh;
+    // Phase B's nodes and their force, read first: a table-driven force
+    // (Kolmogorov rows, a field) then arrives during phase A instead of
+    // adding a memory round trip to phase B.
+    const int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * 4;
+    const int yb = y0 + rb < d.ny ? y0 + rb : d.ny - 1;
+    R FxB[4], FyB[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) force_at<R, FM>(d, x0 + cb + k < d.nx ? x0 + cb + k : d.nx - 1, yb, FxB[k], FyB[k]);
     // The tables: region row rr is lattice row y0 - 1 + rr, region column cc
     // lattice column x0 - 1 + cc, both periodic (a lattice narrower or lower
     // than the region repeats); a row beyond a wall is marked and takes the
     // wall row's offsets.  The pull sources of node (x, y) lie in rows
     // y - 1, y, y + 1 and columns x - 1, x, x + 1, or, where a row is beyond
     // a wall, in the node's own reversed slot.
-    if (threadIdx.x < kRH) {
+    if (threadIdx.x < TL::RH) {
         const int rr = threadIdx.x;
         int y = y0 - 1 + rr;
         bool beyond = false;
@@ -133,7 +160,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         e.rq = row_at<I>(d, in_p ? (yp >= d.ny ? yp - d.ny : yp) : y) * kU;
         e.y = beyond ? -1 : y;
         tab.row[rr] = e;
-    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kRW) {
+    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + TL::RW) {
         const int cc = threadIdx.x - 64;
         const int x = wrap_mod(x0 - 1 + cc, d.nx);
         ColEnt<I> e;
@@ -149,29 +176,32 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 #pragma unroll
     for (int i = 0; i < 9; ++i) so[i] = (I)i * (I)d.dstride * kU;
 
-    // Region node j is region row j / kRW, column j % kRW.  Every thread
-    // issues the loads of all its region nodes before colliding any: nodes
-    // past the region or beyond a wall load from an in-lattice place and
-    // are not stored (the rows beyond a wall are never pulled: bounce-back
-    // reads the node itself).
-    R ga[kPer][9];
+    // Region node j is region row j / rw, column j % rw; the row comes from
+    // a float product, exact here: (j + 1/2) / rw lies at least 1/(2 rw)
+    // from an integer and j < 2^11.  Every thread issues the loads of all
+    // its region nodes before colliding any: nodes past the region or
+    // beyond a wall load from an in-lattice place and are not stored (the
+    // rows beyond a wall are never pulled: bounce-back reads the node
+    // itself).
+    const float inv_rw = 1.0f / (float)rw;
+    R ga[kPer][9], FxA[kPer], FyA[kPer];
     int rra[kPer], cca[kPer], xa[kPer], ya[kPer];
     bool keep[kPer];
-    // A wave whose lanes all lie past the region in the last round skips
-    // its loads and collision (the condition is the same for every lane of
-    // the wave; skipping the idle fourth wave's round took 4096^2 from 142.5
-    // to 151 GLUPS).
-    const bool last = kBlock * (kPer - 1) + (int)(threadIdx.x & ~63u) < kN;
+    // A wave whose lanes all lie past the region in a round skips that
+    // round's loads and collisions (the condition is the same for every lane
+    // of the wave; skipping the idle fourth wave's last round of a full
+    // 64 x 16 tile took 4096^2 from 142.5 to 151 GLUPS).
+    const int wave0 = (int)(threadIdx.x & ~63u);
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
-        if (m == kPer - 1 && !last) {
+        if (kBlock * m + wave0 >= nreg) {
             keep[m] = false;
             continue;
         }
         int j = threadIdx.x + kBlock * m;
-        const bool inr = j < kN;
-        j = inr ? j : kN - 1;
-        const int rr = j / kRW, cc = j - rr * kRW;
+        const bool inr = j < nreg;
+        j = inr ? j : nreg - 1;
+        const int rr = (int)(((float)j + 0.5f) * inv_rw), cc = j - rr * rw;
         const RowEnt<I> re = tab.row[rr];
         const ColEnt<I> ce = tab.col[cc];
         keep[m] = inr && re.y >= 0;
@@ -180,6 +210,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         cca[m] = cc;
         xa[m] = ce.x;
         ya[m] = y;
+        force_at<R, FM>(d, ce.x, y, FxA[m], FyA[m]);
         const bool in_m = !d.bc_y || y >= 1, in_p = !d.bc_y || y + 1 < d.ny;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -196,10 +227,8 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     }
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
-        if (m == kPer - 1 && !last) continue;
-        R Fx, Fy;
-        force_at<R, FM>(d, xa[m], ya[m], Fx, Fy);
-        collide<R, SCH>(ga[m], Fx, Fy, rt);
+        if (kBlock * m + wave0 >= nreg) continue;
+        collide<R, SCH>(ga[m], FxA[m], FyA[m], rt);
         if (keep[m]) {
             // Each value in its storage type as the one-step kernel stores
             // it: rounded to nearest, or stochastically with the operand of
@@ -221,13 +250,13 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int ai = a + ey_of(i), bi = b + ex_of(i);
-                if (ai >= 0 && ai < kTH && bi >= 0 && bi < kTW) lds[i][ai][bi] = rv[i];
+                if (ai >= 0 && ai < TH && bi >= 0 && bi < TW) lds[i][ai][bi] = rv[i];
             }
             // Next to a wall the node's slots that would come from beyond
             // it take the node's own reversed values (nothing else is
             // stored there: nodes beyond a wall are not kept).
             const bool lo = d.bc_y && ya[m] == 0, hi = d.bc_y && ya[m] == d.ny - 1;
-            if ((lo || hi) && a >= 0 && a < kTH && b >= 0 && b < kTW) {
+            if ((lo || hi) && a >= 0 && a < TH && b >= 0 && b < TW) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     if ((ey_of(i) == 1 && lo) || (ey_of(i) == -1 && hi))
@@ -240,7 +269,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 
     // Phase B: 4 consecutive nodes per thread, node (x0 + c + k, y0 + r);
     // slot i of all four is one aligned vector of LDS.
-    const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
+    const int r = rb, c = cb;
     const int y = y0 + r;
     if (y >= d.ny || x0 + c >= d.nx) return;
     R g[4][9];
@@ -252,11 +281,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     }
     Pack<T, 4> q[9];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        R Fx, Fy;
-        force_at<R, FM>(d, x0 + c + k < d.nx ? x0 + c + k : d.nx - 1, y, Fx, Fy);
-        collide<R, SCH>(g[k], Fx, Fy, rt);
-    }
+    for (int k = 0; k < 4; ++k) collide<R, SCH>(g[k], FxB[k], FyB[k], rt);
     if constexpr (S::kDither) {
         // The one-step kernel's stochastic rounding of four nodes, in pairs.
         uint32_t h[4];
@@ -318,50 +343,84 @@ __device__ __forceinline__ void strip_tile(int t, int tiles_x, int tiles_y, int 
     }
 }
 
-template <int ST, int FM, int SCH, typename I>
+template <int ST, int FM, int SCH, typename I, typename TL>
 __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
 {
-    static_assert(kBlock == 256 && kTW == 64 && kTH == 16, "phase B maps 256 threads to 16 x 64 nodes");
-    __shared__ __align__(16) typename Storage<ST>::T lds[9][kTH][kTW];
-    __shared__ TileTabs<I> tab;
+    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
+    __shared__ TileTabs<I, TL> tab;
     // xcd_order gives each XCD a contiguous range of tile numbers, and the
     // strip walk puts a tile's left neighbour one tile and the one above it
     // sw tiles earlier in that range, so the halo lines a tile shares with
     // them are still in that XCD's L2.
-    const int tiles_x = (d.nx + kTW - 1) / kTW, tiles_y = (d.ny + kTH - 1) / kTH;
+    const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
     const int t = (int)xcd_order(blockIdx.x, gridDim.x);
     int tx, ty;
     strip_tile(t, tiles_x, tiles_y, sw, tx, ty);
-    pair_tile<ST, FM, SCH, I>(d, src, tx * kTW, ty * kTH, lds, tab);
+    pair_tile<ST, FM, SCH, I, TL>(d, src, tx * TL::TW, ty * TL::TH, lds, tab);
 }
 
-// Pair substep `pair` of a batch group (tiles numbered lattice by lattice,
-// tile_lat naming each tile's lattice).  A lattice with at least two steps
-// left in this sequence takes two fused steps; one with one step left takes
-// it with the one-step node update (the group's step count may be odd).
-// The buffer parity of these lattices counts launches: pair p reads buffer
-// parity + p.
-template <int ST, int FM, int SCH, typename I>
+// Tile lt of lattice d in batch pair substep `pair`: a lattice with at least
+// two steps left in this sequence takes two fused steps; one with one step
+// left takes it with the one-step node update (the group's step count may
+// be odd).  The buffer parity of these lattices counts launches: pair p
+// reads buffer parity + p.  Within a lattice the tiles take the strip walk.
+template <int ST, int FM, int SCH, typename I, typename TL>
+__device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair,
+                                                typename Storage<ST>::T (&lds)[9][TL::TH][TL::TW],
+                                                TileTabs<I, TL> &tab)
+{
+    const int left = d.steps - 2 * pair;
+    const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
+    int tx, ty;
+    strip_tile((int)lt, tiles_x, tiles_y, tiles_x < kStripTiles ? tiles_x : kStripTiles, tx, ty);
+    const int x0 = tx * TL::TW, y0 = ty * TL::TH;
+    const int src = (d.parity + pair) & 1;
+    if (left >= 2) {
+        pair_tile<ST, FM, SCH, I, TL>(d, src, x0, y0, lds, tab);
+    } else {
+        const int r = threadIdx.x / TL::LPR, c = (threadIdx.x % TL::LPR) * 4;
+        if (y0 + r < d.ny && x0 + c < d.nx) step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
+    }
+}
+
+// Pair substep `pair` of a batch group, one block per tile (tiles numbered
+// lattice by lattice, tile_lat naming each tile's lattice).
+template <int ST, int FM, int SCH, typename I, typename TL>
 __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ lats,
                                                    const int32_t *__restrict__ tile_lat, int64_t ntiles,
                                                    int pair)
 {
-    __shared__ __align__(16) typename Storage<ST>::T lds[9][kTH][kTW];
-    __shared__ TileTabs<I> tab;
+    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
+    __shared__ TileTabs<I, TL> tab;
     const int64_t t = xcd_order(blockIdx.x, ntiles);
     const LatDesc &d = lats[tile_lat[t]];
-    const int left = d.steps - 2 * pair;
-    if (left <= 0) return;  // the whole block: one lattice per tile
-    const int64_t lt = t - d.tile0;
-    const int tiles_x = (d.nx + kTW - 1) / kTW;
-    const int ty = (int)(lt / tiles_x);
-    const int x0 = (int)(lt - (int64_t)ty * tiles_x) * kTW, y0 = ty * kTH;
-    const int src = (d.parity + pair) & 1;
-    if (left >= 2) {
-        pair_tile<ST, FM, SCH, I>(d, src, x0, y0, lds, tab);
-    } else {
-        const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
-        if (y0 + r < d.ny && x0 + c < d.nx) step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
+    if (d.steps - 2 * pair <= 0) return;  // the whole block: one lattice per tile
+    batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds, tab);
+}
+
+// The same with a persistent grid: block b walks one contiguous range of
+// the group's tiles (neighbouring tiles of a lattice one after another), and
+// looks up the next tile's lattice while the current tile runs.  Every
+// thread of a block runs every iteration, so the barriers inside match.
+template <int ST, int FM, int SCH, typename I, typename TL>
+__global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ lats,
+                                                    const int32_t *__restrict__ tile_lat, int64_t ntiles,
+                                                    int pair)
+{
+    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
+    __shared__ TileTabs<I, TL> tab;
+    const int64_t G = gridDim.x;
+    const int64_t b = xcd_order(blockIdx.x, G);
+    const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
+    int j = lo < hi ? tile_lat[lo] : 0;
+    for (int64_t t = lo; t < hi; ++t) {
+        const int jn = t + 1 < hi ? tile_lat[t + 1] : j;
+        const LatDesc &d = lats[j];
+        if (d.steps - 2 * pair > 0) batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds, tab);
+        j = jn;
+        // The next tile's tables and phase A overwrite what this tile's
+        // phase B still reads.
+        __syncthreads();
     }
 }
 
@@ -371,21 +430,22 @@ __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ l
 template <int ST>
 hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
 {
-    const int64_t tiles = (int64_t)((d.nx + kTW - 1) / kTW) * ((d.ny + kTH - 1) / kTH);
+    using TL = T64x16;
+    const int64_t tiles = (int64_t)((d.nx + TL::TW - 1) / TL::TW) * ((d.ny + TL::TH - 1) / TL::TH);
     const dim3 grid((unsigned)tiles), block(kBlock);
     // Elements of one buffer: whole row blocks of bstride elements.
     const int64_t rows = (int64_t)1 << d.rshift;
     const int64_t elems = (d.ny + rows - 1) / rows * d.bstride;
     const bool small = elems * (int64_t)sizeof(typename Storage<ST>::T) + 4096 < ((int64_t)1 << 32);
-    const int tiles_x = (d.nx + kTW - 1) / kTW;
+    const int tiles_x = (d.nx + TL::TW - 1) / TL::TW;
     const int sw = tiles_x < kStripTiles ? tiles_x : kStripTiles;
     switch (d.force_mode * 2 + d.scheme) {
-#define CLBM_S2(FM, SCH)                                                          \
-    case FM * 2 + SCH:                                                            \
-        if (small)                                                                \
-            k_step2<ST, FM, SCH, uint32_t><<<grid, block, 0, s>>>(d, src, sw);    \
-        else                                                                      \
-            k_step2<ST, FM, SCH, int64_t><<<grid, block, 0, s>>>(d, src, sw);     \
+#define CLBM_S2(FM, SCH)                                                              \
+    case FM * 2 + SCH:                                                                \
+        if (small)                                                                    \
+            k_step2<ST, FM, SCH, uint32_t, TL><<<grid, block, 0, s>>>(d, src, sw);    \
+        else                                                                          \
+            k_step2<ST, FM, SCH, int64_t, TL><<<grid, block, 0, s>>>(d, src, sw);     \
         break;
         CLBM_S2(FM_CONST, SCH_CONSISTENT)
         CLBM_S2(FM_CONST, SCH_GUO_LBL)
@@ -400,18 +460,26 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int ST>
-hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
-                            int pair, hipStream_t s)
+namespace {
+template <int ST, typename TL>
+hipError_t batch2_shape(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
+                        int pair, int grid, hipStream_t s)
 {
-    const dim3 grid((unsigned)ntiles), block(kBlock);
+    const dim3 g((unsigned)(grid > 0 ? grid : ntiles)), block(kBlock);
     switch (key) {
-#define CLBM_B2(FM, SCH)                                                                      \
-    case FM * 2 + SCH:                                                                        \
-        if (small)                                                                            \
-            k_batch2<ST, FM, SCH, uint32_t><<<grid, block, 0, s>>>(lats, tile_lat, ntiles, pair); \
-        else                                                                                  \
-            k_batch2<ST, FM, SCH, int64_t><<<grid, block, 0, s>>>(lats, tile_lat, ntiles, pair);  \
+#define CLBM_B2(FM, SCH)                                                                                   \
+    case FM * 2 + SCH:                                                                                     \
+        if (grid > 0) {                                                                                    \
+            if (small)                                                                                     \
+                k_batch2p<ST, FM, SCH, uint32_t, TL><<<g, block, 0, s>>>(lats, tile_lat, ntiles, pair);    \
+            else                                                                                           \
+                k_batch2p<ST, FM, SCH, int64_t, TL><<<g, block, 0, s>>>(lats, tile_lat, ntiles, pair);     \
+        } else {                                                                                           \
+            if (small)                                                                                     \
+                k_batch2<ST, FM, SCH, uint32_t, TL><<<g, block, 0, s>>>(lats, tile_lat, ntiles, pair);     \
+            else                                                                                           \
+                k_batch2<ST, FM, SCH, int64_t, TL><<<g, block, 0, s>>>(lats, tile_lat, ntiles, pair);      \
+        }                                                                                                  \
         break;
         CLBM_B2(FM_CONST, SCH_CONSISTENT)
         CLBM_B2(FM_CONST, SCH_GUO_LBL)
@@ -424,6 +492,15 @@ hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+}  // namespace
+
+template <int ST>
+hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
+                            int pair, int shape, int grid, hipStream_t s)
+{
+    if (shape == kTile32x32) return batch2_shape<ST, T32x32>(lats, tile_lat, ntiles, key, small, pair, grid, s);
+    return batch2_shape<ST, T64x16>(lats, tile_lat, ntiles, key, small, pair, grid, s);
 }
 
 }  // namespace clbm

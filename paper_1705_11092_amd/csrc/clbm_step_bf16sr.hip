@@ -7,7 +7,7 @@ template hipError_t launch_step_st<ST_BF16_SR>(const LatDesc &, int, int, size_t
 template hipError_t launch_resident_st<ST_BF16_SR>(const LatDesc &, int, int, hipStream_t);
 template hipError_t launch_step2_st<ST_BF16_SR>(const LatDesc &, int, hipStream_t);
 template hipError_t launch_batch2_st<ST_BF16_SR>(const LatDesc *, const int32_t *, int64_t, int, bool, int,
-                                          hipStream_t);
+                                          int, int, hipStream_t);
 template hipError_t launch_batch_st<ST_BF16_SR>(const LatDesc *, const int32_t *, int64_t, int, int,
                                          int, int, size_t, hipStream_t);
 }  // namespace clbm

@@ -199,7 +199,10 @@ def test_batch_pairs_equal_single_steps():
     counts = [70, 33, 5, 1, 0, 9, 12, 37, 8]
     more = [3, 2, 1, 4, 7, 0, 5, 3, 0]
     out = []
-    for pairs in (False, True):
+    # Singly, then in pairs with each two-step variant (tile shapes 64 x 16
+    # and 32 x 32, one block per tile or persistent blocks): variants
+    # 0 .. 3 share the single-step part and differ in the two-step part.
+    for pairs, variant in ((False, 0), (True, 0), (True, 1), (True, 2), (True, 3)):
         lats = []
         for k, (nx, ny, bc, force, storage, inplace) in enumerate(shapes):
             wl = inputs.random_state(nx, ny, seed=970 + k, bc_y=bc, force=force, amp_f=1e-3,
@@ -208,6 +211,7 @@ def test_batch_pairs_equal_single_steps():
             lat.step_pairs = pairs
             lats.append(lat)
         b = clbm.Batch(lats)
+        b.variant = variant
         b.step_each(counts)
         b.step_each(more)
         b.step(40)
@@ -216,8 +220,9 @@ def test_batch_pairs_equal_single_steps():
         b.close()
         for lat in lats:
             lat.close()
-    for k, (a, c) in enumerate(zip(out[0], out[1])):
-        assert np.array_equal(a, c), f"lattice {k} {shapes[k]}"
+    for o in out[1:]:
+        for k, (a, c) in enumerate(zip(out[0], o)):
+            assert np.array_equal(a, c), f"lattice {k} {shapes[k]}"
 
 
 def test_batch_follows_a_force_change():

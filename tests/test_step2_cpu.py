@@ -1,21 +1,25 @@
 """Host-side checks of the two-step kernel's index maps (no GPU).
 
-The two-step kernel walks its 64 x 16 tiles in vertical strips of up to 8
-tile columns, collides step n + 1 on each tile's 66 x 18 region (the tile and
-a one-node halo) and writes slot i of a region node straight into the LDS
-entry of the tile node that pulls it (Eq. 10), or, next to a bounce-back
-wall, the node's own reversed slot into the entry its absent neighbour would
-fill.  These tests restate that arithmetic and check that the walk visits
-every tile once and that every LDS entry phase B reads is written exactly
-once, by the source the pull with half-way bounce-back names.
+The two-step kernel walks its tiles (64 x 16 or 32 x 32 nodes) in vertical
+strips of up to 8 tile columns, collides step n + 1 on each tile's region
+(the tile's nodes inside the lattice and a one-node halo: at most 66 x 18 or
+34 x 34 nodes, less for a tile at the lattice's right or lower edge) and
+writes slot i of a region node straight into the LDS entry of the tile node
+that pulls it (Eq. 10), or, next to a bounce-back wall, the node's own
+reversed slot into the entry its absent neighbour would fill.  These tests
+restate that arithmetic and check that the walk visits every tile once,
+that every LDS entry phase B reads is written exactly once, by the source
+the pull with half-way bounce-back names, and that the region row of a
+region node comes out exact from its float product.
 """
 import pytest
 
 EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
 OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
-TW, TH, STRIP = 64, 16, 8
-RW, RH = TW + 2, TH + 2
+STRIP = 8
+SHAPES = [(64, 16), (32, 32)]
+TW, TH = 64, 16
 
 
 def strip_tile(t, tiles_x, tiles_y, sw):
@@ -42,32 +46,34 @@ def test_strip_walk_visits_every_tile_once(nx, ny):
         assert seen[sw] == (seen[0][0], seen[0][1] + 1)
 
 
-def _phase_a_writes(nx, ny, bc, x0, y0):
+def _phase_a_writes(nx, ny, bc, x0, y0, tw=TW, th=TH):
     """Map (slot, tile row, tile column) -> (source x, source y, source slot)
     as phase A writes it, from the region's row and column tables."""
+    rw = min(tw, nx - x0) + 2
+    rh = min(th, ny - y0) + 2
     rows = []
-    for rr in range(RH):
+    for rr in range(rh):
         y = y0 - 1 + rr
         beyond = bool(bc) and (y < 0 or y >= ny)
         if beyond:
             y = 0 if y < 0 else ny - 1
         rows.append((y % ny, beyond))
-    cols = [(x0 - 1 + cc) % nx for cc in range(RW)]
+    cols = [(x0 - 1 + cc) % nx for cc in range(rw)]
     writes = {}
-    for rr in range(RH):
+    for rr in range(rh):
         y, beyond = rows[rr]
         if beyond:
             continue
-        for cc in range(RW):
+        for cc in range(rw):
             x = cols[cc]
             a, b = rr - 1, cc - 1
             for i in range(9):
                 ai, bi = a + EY[i], b + EX[i]
-                if 0 <= ai < TH and 0 <= bi < TW:
+                if 0 <= ai < th and 0 <= bi < tw:
                     assert (i, ai, bi) not in writes, "written twice"
                     writes[(i, ai, bi)] = (x, y, i)
             lo, hi = bc and y == 0, bc and y == ny - 1
-            if (lo or hi) and 0 <= a < TH and 0 <= b < TW:
+            if (lo or hi) and 0 <= a < th and 0 <= b < tw:
                 for i in range(9):
                     if (EY[i] == 1 and lo) or (EY[i] == -1 and hi):
                         assert (i, a, b) not in writes, "wall entry written twice"
@@ -75,19 +81,21 @@ def _phase_a_writes(nx, ny, bc, x0, y0):
     return writes
 
 
+@pytest.mark.parametrize("tw,th", SHAPES)
 @pytest.mark.parametrize("nx,ny,bc", [(300, 70, 1), (300, 70, 0), (65, 17, 1), (33, 1, 1), (70, 2, 1),
-                                      (2, 2, 0), (19, 1, 0), (1, 17, 1), (129, 33, 1), (200, 40, 0)])
-def test_lds_entries_hold_the_pulled_values(nx, ny, bc):
-    tiles_x, tiles_y = (nx + TW - 1) // TW, (ny + TH - 1) // TH
+                                      (2, 2, 0), (19, 1, 0), (1, 17, 1), (129, 33, 1), (200, 40, 0),
+                                      (40, 100, 0), (31, 33, 1)])
+def test_lds_entries_hold_the_pulled_values(nx, ny, bc, tw, th):
+    tiles_x, tiles_y = (nx + tw - 1) // tw, (ny + th - 1) // th
     for ty in range(tiles_y):
         for tx in range(tiles_x):
-            x0, y0 = tx * TW, ty * TH
-            writes = _phase_a_writes(nx, ny, bc, x0, y0)
-            for r in range(TH):
+            x0, y0 = tx * tw, ty * th
+            writes = _phase_a_writes(nx, ny, bc, x0, y0, tw, th)
+            for r in range(th):
                 y = y0 + r
                 if y >= ny:
                     continue
-                for c in range(TW):
+                for c in range(tw):
                     x = x0 + c
                     if x >= nx:
                         continue
@@ -98,3 +106,17 @@ def test_lds_entries_hold_the_pulled_values(nx, ny, bc):
                         else:
                             want = ((x - EX[i]) % nx, ys % ny, i)
                         assert writes.get((i, r, c)) == want, (nx, ny, bc, tx, ty, r, c, i)
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+def test_region_row_from_float_product_is_exact(tw, th):
+    # rr = (int)((j + 1/2) * fl(1/rw)) in FP32 for every region size the
+    # kernel meets and every index a thread takes (j < 5 * 256).
+    import numpy as np
+    for rw in range(3, tw + 3):
+        inv = np.float32(1.0) / np.float32(rw)
+        for rh in range(3, th + 3):
+            n = rw * rh
+            j = np.arange(min(n, 5 * 256), dtype=np.int64)
+            rr = ((j.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int64)
+            assert np.array_equal(rr, j // rw), (rw, rh)
