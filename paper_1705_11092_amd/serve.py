@@ -15,6 +15,12 @@ The batched kernel updates every node with exactly the arithmetic of a
 single-lattice step, so a request's result does not depend on what else
 was in the batch.
 
+A watchdog guards against the method's one failure mode, divergence (an
+unstable choice of rates, Sec. IV C): every ``watch_every`` ticks the
+server has the FP64 mass and momentum of every active request reduced on
+the device behind the tick, and a request whose totals are NaN or Inf is
+failed and its slot freed at once, instead of running out its step budget.
+
 The server is backend-agnostic: ``GpuBackend`` drives the HIP library; a
 test backend can model time instead.
 """
@@ -180,6 +186,21 @@ class GpuBackend:
             host.append(h)
         return _Pending(slot, host)
 
+    def watch(self, slot):
+        """Enqueue the FP64 totals {mass, momentum} of a request's state
+        (clbm_moments_noalloc: no allocation in the library, no wait) and
+        their copy to pinned host memory; read them with watched() once a
+        later fence has passed."""
+        torch = self.torch
+        dev = torch.empty(3, dtype=torch.float64, device=self.device)
+        slot.moments_noalloc(totals=dev)
+        host = torch.empty(3, dtype=torch.float64, pin_memory=True)
+        host.copy_(dev, non_blocking=True)
+        return host
+
+    def watched(self, token):
+        return tuple(float(v) for v in token.numpy())
+
     def fence(self):
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
@@ -213,13 +234,16 @@ class Server:
     """Admit, batch and complete requests as they arrive (see module doc)."""
 
     def __init__(self, backend, clock=None, max_active: int = 1024, tick_s: float = 0.02,
-                 min_tick: int = 32, max_tick: int = 4096, log=None):
+                 min_tick: int = 32, max_tick: int = 4096, log=None, watch_every: int = 8):
         self.backend = backend
         self.clock = clock or WallClock()
         self.max_active = max_active
         self.tick_s = tick_s
         self.min_tick, self.max_tick = min_tick, max_tick
         self.log = log
+        # Watchdog period in ticks (0: off; the final fields are checked
+        # either way).
+        self.watch_every = watch_every
         self._cancel = set()
 
     def cancel(self, rid: int):
@@ -241,7 +265,8 @@ class Server:
         used = peak = 0
         lups = 0.0
         ticks = max_act = 0
-        inflight = None  # (event, [(rid, pending, footprint)])
+        inflight = None  # (event, [(rid, pending, footprint, slot)], [(rid, watch token)])
+        watch = self.watch_every > 0 and hasattr(be, "watch")
         t0 = clock.now()
 
         def now():
@@ -249,9 +274,22 @@ class Server:
 
         def finalize(batch):
             nonlocal used
-            ev, items = batch
+            ev, items, watched = batch
             be.wait(ev)
             t = now()
+            # Watchdog: fail a still active request whose totals diverged.
+            for rid, token in watched:
+                if rid not in active:
+                    continue
+                tot = be.watched(token)
+                if not all(math.isfinite(v) for v in tot):
+                    req, slot, left, fp = active.pop(rid)
+                    r = results[rid]
+                    r.status, r.finished, r.totals = "failed", t, tot
+                    r.message = (f"diverged: non-finite mass or momentum within its first "
+                                 f"{req.workload.steps - left} of {req.workload.steps} steps (watchdog)")
+                    be.close(slot)
+                    used -= fp
             for rid, pend, fp, slot in items:
                 rho, ux, uy = be.collect(pend)
                 r = results[rid]
@@ -319,10 +357,13 @@ class Server:
                     if a[2] == 0:
                         done_items.append((r, be.finish(a[1]), a[3], a[1]))
                         del active[r]
+                watched = []
+                if watch and ticks % self.watch_every == 0:
+                    watched = [(r, be.watch(active[r][1])) for r in active]
                 ev = be.fence()
                 if inflight is not None:
                     finalize(inflight)
-                inflight = (ev, done_items)
+                inflight = (ev, done_items, watched)
             elif inflight is not None:
                 finalize(inflight)
                 inflight = None

@@ -3,8 +3,9 @@ lattices with the oracle and models device time on a virtual clock.
 
 Covered: admission by footprint, first-fit order, rejection of requests
 larger than the budget, slot reuse, cancellation, fault isolation (a
-non-finite request fails alone), results equal to solo runs, and the
-latency statistics.
+non-finite request fails alone), the divergence watchdog (a diverging
+request fails long before its step budget runs out), results equal to solo
+runs, and the latency statistics.
 """
 import dataclasses
 import math
@@ -70,6 +71,13 @@ class FakeBackend:
 
     def finish(self, slot):
         return oracle.moments(slot.f, slot.fx, slot.fy)
+
+    def watch(self, slot):
+        rho, ux, uy = oracle.moments(slot.f, slot.fx, slot.fy)
+        return (float(rho.sum()), float((rho * ux).sum()), float((rho * uy).sum()))
+
+    def watched(self, token):
+        return token
 
     def fence(self):
         return self.busy_until
@@ -178,6 +186,40 @@ def test_a_nonfinite_request_fails_alone():
     req = reqs[0]
     solo = run_alone(FakeBackend(VirtualClock(), capacity=10**9), req)
     assert np.array_equal(rep.results[req.rid].ux, solo.ux)
+
+
+def test_watchdog_stops_a_diverging_request_early():
+    # A request whose state is NaN from the start and whose step budget is
+    # 200,000 steps: the watchdog (every 4 ticks of at most 16 steps) fails
+    # it within its first 64 + 16 steps and frees its slot; the others finish
+    # and equal their solo runs.
+    reqs = _stream(count=6)
+    bad = dataclasses.replace(reqs[1], workload=dataclasses.replace(reqs[1].workload, steps=200_000))
+    bad.workload.rho = bad.workload.rho.copy()
+    bad.workload.rho[2, 3] = math.nan
+    reqs[1] = bad
+    clock = VirtualClock()
+    be = FakeBackend(clock, capacity=10**9)
+    rep = Server(be, clock=clock, min_tick=8, max_tick=16, watch_every=4).run(reqs)
+    r = rep.results[bad.rid]
+    assert r.status == "failed" and "watchdog" in r.message, r.message
+    nodes = bad.workload.nx * bad.workload.ny
+    others = sum(q.workload.nx * q.workload.ny * q.workload.steps for q in reqs if q.rid != bad.rid)
+    assert rep.lups - others <= (4 * 16 + 16) * nodes
+    for q in reqs:
+        if q.rid == bad.rid:
+            continue
+        assert rep.results[q.rid].status == "done"
+        solo = run_alone(FakeBackend(VirtualClock(), capacity=10**9), q)
+        assert np.array_equal(rep.results[q.rid].ux, solo.ux)
+    assert all(s.closed for s in be.opened)
+    # With the watchdog off the same request runs out its budget first.
+    clock = VirtualClock()
+    be = FakeBackend(clock, capacity=10**9)
+    rep = Server(be, clock=clock, min_tick=8, max_tick=16, watch_every=0).run(
+        [dataclasses.replace(bad, workload=dataclasses.replace(bad.workload, steps=400))])
+    assert rep.results[bad.rid].status == "failed"
+    assert rep.lups == 400 * nodes
 
 
 def test_tick_length_is_a_bounded_power_of_two():
