@@ -484,6 +484,7 @@ int clbm_set_force(clbm_handle *h, int32_t kind, const double *params, const dou
             d.sc_g = params[0];
             d.sc_psi0 = params[1];
             d.sc_rho = params[2];
+            d.sc_psic = params[1] * std::exp(-params[2] / d.rho0);
         }
         d.force = h->force_buf;
         d.Fx = d.Fy = 0.0;

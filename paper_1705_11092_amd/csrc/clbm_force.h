@@ -27,7 +27,9 @@ __device__ __forceinline__ void force_at(const LatDesc &d, int x, int y, R &Fx, 
     } else {
         // Shan-Chen interaction (Sec. IV C): F = -G psi(x) sum_i w_i psi(x + e_i) e_i,
         // w = 1/3 for the four axis neighbours and 1/12 for the diagonals;
-        // periodic in x and y.
+        // periodic in x and y.  The plane holds q = psi - psi(rho0); the
+        // constant part drops out of the weighted sum (sum_i w_i e_i = 0),
+        // so the sum is formed from q and only psi(x) adds it back.
         const R *psi = static_cast<const R *>(d.force);
         const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
         const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
@@ -37,7 +39,7 @@ __device__ __forceinline__ void force_at(const LatDesc &d, int x, int y, R &Fx, 
                      twelfth * ((psi[rp + xp] - psi[rp + xm]) + (psi[rm + xp] - psi[rm + xm]));
         const R sy = third * (psi[rp + x] - psi[rm + x]) +
                      twelfth * ((psi[rp + xp] + psi[rp + xm]) - (psi[rm + xp] + psi[rm + xm]));
-        const R g = -R(d.sc_g) * psi[r0 + x];
+        const R g = -R(d.sc_g) * (R(d.sc_psic) + psi[r0 + x]);
         Fx = g * sx;
         Fy = g * sy;
     }

@@ -72,6 +72,7 @@ struct LatDesc {
     double inv_tpr;      // 1 / tpr, for the tile decode
     double Fx, Fy;       // FM_CONST force density
     double sc_g, sc_psi0, sc_rho;  // FM_SC: G, psi0 and rho_ref of psi = psi0 exp(-rho_ref/rho)
+    double sc_psic;                // FM_SC: psi(rho0); the psi plane holds psi - sc_psic
     double rho0;
     // Relaxation and force weights of the collision (set_rates).
     double nap, nam;       // -(sb + s2)/2, -(sb - s2)/2

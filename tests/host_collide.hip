@@ -41,4 +41,21 @@ void host_collide_f32(const double *f, double Fx, double Fy, const double *s6, d
 {
     host_collide<float>(f, Fx, Fy, s6, rho0, scheme, out);
 }
+// n nodes of FP32 deviations g (node-major, 9 per node) collided in place in
+// FP32 arithmetic with per-node forces (FP32): the kernel's node update for
+// an FP32 lattice, for host emulations of whole runs.
+void host_collide_f32_dev(int64_t n, float *g, const float *fx, const float *fy, const double *s6,
+                          double rho0, int scheme)
+{
+    clbm::LatDesc d{};
+    d.rho0 = rho0;
+    clbm::set_rates(d, s6[1], s6[2], s6[3], s6[4], s6[5], scheme);
+    const clbm::Rates<float> rt = clbm::rates_of<float>(d);
+    for (int64_t k = 0; k < n; ++k) {
+        if (d.scheme == clbm::SCH_GUO_LBL)
+            clbm::collide<float, clbm::SCH_GUO_LBL>(g + 9 * k, fx[k], fy[k], rt);
+        else
+            clbm::collide<float, clbm::SCH_CONSISTENT>(g + 9 * k, fx[k], fy[k], rt);
+    }
+}
 }

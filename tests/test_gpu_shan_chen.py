@@ -4,10 +4,12 @@ Parity: the HIP path (a psi pass, then the fused step reading the
 neighbours' psi) against the oracle (numpy force from the density, then the
 oracle step), on a droplet, a ragged slab and a droplet under the
 Lycett-Brown & Luo scheme, element by element.  Tolerances on E2:
-FP64 1e-12 (u) and 1e-13 (rho).  FP32 1e-4 on u, measured 3.8e-6 to 3.0e-5:
-the velocities here are spurious currents of 4e-3 to 4e-2, and the FP32
-rounding of psi and of the nearly cancelling neighbour sum in the bulk
-leaves about 1e-7 of absolute velocity per node.  16-bit storage resolves
+FP64 1e-12 (u) and 1e-13 (rho).  FP32 5e-5 on u, measured 3.8e-6 to 3.3e-5:
+the velocities here are spurious currents of 4e-3 to 4e-2, small against the
+populations of densities up to 2.8; a host emulation of the FP32 path (the
+kernel's own node update on FP32 deviations, tests/test_storage_floor_cpu.py)
+gives 3.4e-5 on the slab, and FP32 storage alone 1.3e-5, so these errors are
+the floor of FP32, above the 1e-5 of the smooth flows.  16-bit storage resolves
 the populations of a density near 2.8 to 2^-11 (FP16) or 2^-8 (BF16) of
 their size, the same order as these velocities: the stated bounds are
 measured (FP16 u 1.4e-2 to 0.15, rho up to 9.2e-4; BF16 rho up to 5.1e-3,
@@ -35,7 +37,7 @@ from tests.gpu_util import e2_u, gpu_lattice, gpu_run, log, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-TOL_U = {"f64": 1e-12, "f32": 1e-4, "f16": 0.3, "f16sr": 0.3, "bf16sr": None}
+TOL_U = {"f64": 1e-12, "f32": 5e-5, "f16": 0.3, "f16sr": 0.3, "bf16sr": None}
 TOL_RHO = {"f64": 1e-13, "f32": 1e-6, "f16": 2e-3, "f16sr": 2e-3, "bf16sr": 1e-2}
 
 
