@@ -265,7 +265,7 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     the summary bench.py reports as roofline.traffic."""
     import statistics
     csvs = [os.path.join(d, "run_counter_collection.csv") for d in dirs]
-    step = "k_step2<1, 0, 0, unsigned int>"
+    step = "k_step2<1, 0, 0, unsigned int"
     fetch = _counter_values(csvs[0], step, "FETCH_SIZE")
     write = _counter_values(csvs[1], step, "WRITE_SIZE")
     cf = statistics.median(_counter_values(csvs[2], "copyBuffer", "FETCH_SIZE"))
@@ -276,11 +276,11 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     wr = statistics.median(write) * 1024.0 * ws
     alg = BYTES_PER_LUP["f32"] * n * n
     base = "rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 bench.py {a}"
-    step_args = "--steps 6 --warmup 0 --no-cpu-baseline --no-extra"
+    step_args = "--steps 6 --warmup 0 --reps 1 --no-cpu-baseline --no-extra"
     copy_args = f"--calibrate-copy {copy_bytes}"
     out = {
-        "kernel": "clbm::k_step2<1, 0, 0, unsigned int> (two fused steps per launch; FP32 deviations, constant "
-                  "force, consistent scheme)",
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16>> (two fused steps per launch; FP32 "
+                  "deviations, constant force, consistent scheme, 64 x 16 tiles)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),
         "commands": [base.format(c="FETCH_SIZE", d=dirs[0], a=step_args),
@@ -307,7 +307,7 @@ def valu_summary(d: str, n: int = 4096):
     with the hash of the kernel sources it was taken on."""
     import csv
     import statistics
-    step = "k_step2<1, 0, 0, unsigned int>"
+    step = "k_step2<1, 0, 0, unsigned int"
     per = {}
     with open(os.path.join(d, "run_counter_collection.csv"), newline="") as fh:
         for row in csv.DictReader(fh):
@@ -323,12 +323,12 @@ def valu_summary(d: str, n: int = 4096):
     waves = statistics.median(e["SQ_WAVES"] for e in per.values())
     clocks = [e["GRBM_GUI_ACTIVE"] / 8.0 / e["ns"] for e in per.values() if e.get("ns")]
     out = {
-        "kernel": "clbm::k_step2<1, 0, 0, unsigned int> (two fused steps per launch; FP32 deviations, constant "
-                  "force, consistent scheme)",
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16>> (two fused steps per launch; FP32 "
+                  "deviations, constant force, consistent scheme, 64 x 16 tiles)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),
         "command": f"rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE --output-format csv -d {d} -o run "
-                   "-- python3 bench.py --steps 6 --warmup 0 --no-cpu-baseline --no-extra",
+                   "-- python3 bench.py --steps 6 --warmup 0 --reps 1 --no-cpu-baseline --no-extra",
         "dispatches": len(per), "valu_wave_insts_per_launch": valu, "waves_per_launch": waves,
         "valu_insts_per_wave": round(valu / waves, 1),
         "valu_insts_per_node_update": round(valu * 64 / (2 * n * n), 1),

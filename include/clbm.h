@@ -300,7 +300,7 @@ double clbm_s_from_nu(double nu);
 
 /* A batch advances many independent lattices (any sizes, storages, forces,
  * rates, y boundaries and streaming forms; not Shan-Chen) with one
- * persistent kernel launch per time step and kernel kind.
+ * kernel launch per time step (or per fused pair of steps) and kernel kind.
  * Each node is updated by exactly the arithmetic of clbm_step, so a
  * lattice's result is bitwise the same alone and in any batch. */
 typedef struct clbm_batch clbm_batch;
@@ -322,17 +322,25 @@ int clbm_batch_step(clbm_batch *b, int64_t nsteps);
 int clbm_batch_step_each(clbm_batch *b, const int64_t *nsteps);
 
 /* Time the kernel variants of the batch on its own lattices and keep the
- * fastest (results do not depend on the variant).  With cache_path set,
- * look the choice up first and record it after, keyed by architecture and
- * batch shape.  *chosen (optional) receives the variant index.  The timed
- * launches leave every lattice's state untouched: with two buffers they
- * write the spare one, in-place lattices write a scratch allocation the
- * size of the largest of them (stream-ordered, freed on return).
+ * fastest (results do not depend on the variant).  A variant has two parts:
+ * one for the lattices that step one step per launch (bytes per thread per
+ * direction, occupancy cap, persistent grid) and one for those that step
+ * in fused pairs (tile shape 64 x 16 or 32 x 32 nodes, one block per tile or
+ * persistent blocks walking the tiles).  The first part is chosen on the
+ * lattices that step singly, timing one step of each, then the second on
+ * those that step in pairs, timing one fused pair of each.  With cache_path
+ * set, look the choice up first and record it after, keyed by architecture,
+ * variant set and batch shape.  *chosen (optional) receives the variant
+ * index.  The timed launches leave every lattice's state untouched: with
+ * two buffers they write the spare one, in-place lattices write a scratch
+ * allocation the size of the largest of them (stream-ordered, freed on
+ * return).
  * Errors: CLBM_ESTATE (a lattice without state), CLBM_EINVAL (Shan-Chen),
  * CLBM_EHIP. */
 int clbm_batch_autotune(clbm_batch *b, const char *cache_path, int32_t *chosen);
 
-/* Number of kernel variants, and the one in use (settable). */
+/* Number of kernel variants (single-step parts x two-step parts), and the
+ * one in use (settable). */
 int32_t clbm_batch_variant_count(void);
 int clbm_batch_set_variant(clbm_batch *b, int32_t variant);
 int32_t clbm_batch_get_variant(const clbm_batch *b);
