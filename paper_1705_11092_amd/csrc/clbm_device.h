@@ -157,6 +157,30 @@ template <> struct Storage<ST_BF16_SR> {
     }
 };
 
+// Two values rounded to nearest into the storage type.  For the 16-bit
+// types one packed conversion (v_cvt_pk_f16_f32, v_cvt_pk_bf16_f32) rounds
+// both, with the same round-to-nearest-even as the conversion of one value,
+// so a value gets the same bits whether it is converted alone or in a pair.
+// dst points to two consecutive elements (the pair lands as one 32-bit
+// word for the 16-bit types).
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+template <int ST>
+__device__ __forceinline__ void round_pair(typename Storage<ST>::R a, typename Storage<ST>::R b,
+                                           typename Storage<ST>::T *dst)
+{
+    using S = Storage<ST>;
+    if constexpr (ST == ST_F16) {
+        const half2_t h = __builtin_convertvector(float2v_t{fp32_value(a), fp32_value(b)}, half2_t);
+        __builtin_memcpy(dst, &h, sizeof h);
+    } else if constexpr (ST == ST_BF16) {
+        const bfloat2_t h = __builtin_convertvector(float2v_t{fp32_value(a), fp32_value(b)}, bfloat2_t);
+        __builtin_memcpy(dst, &h, sizeof h);
+    } else {
+        dst[0] = S::from_r(a);
+        dst[1] = S::from_r(b);
+    }
+}
+
 // 32-bit integer finaliser: xor-shift-multiply in MurmurHash3's fmix32
 // structure, with the shifts and multipliers of "lowbias32", found by
 // Chris Wellons' hash-prospector search (public domain, 2018).

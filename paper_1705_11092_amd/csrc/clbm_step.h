@@ -151,7 +151,12 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) q[i].v[k] = S::from_r(g[k][i]);
+            for (int k = 0; k < VEC; k += 2) {
+                if (k + 1 < VEC)
+                    round_pair<ST>(g[k][i], g[k + 1][i], &q[i].v[k]);
+                else
+                    q[i].v[k] = S::from_r(g[k][i]);
+            }
     }
 
     if (!AA || src == 0) {

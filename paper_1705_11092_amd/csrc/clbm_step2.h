@@ -241,7 +241,8 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
                 for (int i = 0; i < 9; ++i) rv[i] = S::from_r_sr(ga[m][i], sr_operand(h, i));
             } else {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) rv[i] = S::from_r(ga[m][i]);
+                for (int i = 0; i < 8; i += 2) round_pair<ST>(ga[m][i], ga[m][i + 1], &rv[i]);
+                rv[8] = S::from_r(ga[m][8]);
             }
             // Tile coordinates of the node; slot i goes to the tile node
             // that pulls it, (a + e_y,i, b + e_x,i), when that node is in
@@ -301,9 +302,9 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 4; k += 2)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) q[i].v[k] = S::from_r(g[k][i]);
+            for (int i = 0; i < 9; ++i) round_pair<ST>(g[k][i], g[k + 1][i], &q[i].v[k]);
     }
     const I ob = row_at<I>(d, y) + (I)(x0 + c);
     if (x0 + c + 4 <= d.nx) {
