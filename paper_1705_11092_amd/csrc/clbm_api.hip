@@ -54,14 +54,14 @@ int elem_bytes(int storage)
 }
 
 // Elements of one direction's run within a lattice row (padded).
-int64_t pitch_of(int nx) { return ((int64_t)nx + clbm::kRowAlign - 1) / clbm::kRowAlign * clbm::kRowAlign; }
+int64_t pitch_of(int nx, int eb) { return clbm::row_pitch(nx, eb); }
 
 // log2 of the rows per row block: double while one direction's run in a
 // block is shorter than kBlockRunBytes and the block stays within the
 // lattice height.
 int row_shift(int nx, int ny, int eb)
 {
-    const int64_t run = pitch_of(nx) * eb;
+    const int64_t run = pitch_of(nx, eb) * eb;
     int sh = 0;
     while (run << sh < clbm::kBlockRunBytes && (2LL << sh) <= ny) ++sh;
     return sh;
@@ -337,8 +337,8 @@ size_t clbm_buffer_bytes(int32_t nx, int32_t ny, int32_t storage)
 {
     const int eb = elem_bytes(storage);
     if (nx < 1 || ny < 1 || eb == 0) return 0;
-    if (pitch_of(nx) * rows_allocated(nx, ny, eb) > (int64_t)INT32_MAX) return 0;
-    return (size_t)(9 * pitch_of(nx) * rows_allocated(nx, ny, eb) * eb + clbm::kTailGuardBytes);
+    if (pitch_of(nx, eb) * rows_allocated(nx, ny, eb) > (int64_t)INT32_MAX) return 0;
+    return (size_t)(9 * pitch_of(nx, eb) * rows_allocated(nx, ny, eb) * eb + clbm::kTailGuardBytes);
 }
 
 int clbm_create(const clbm_config *cfg, clbm_handle **out)
@@ -348,7 +348,7 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     *out = nullptr;
     if (cfg->nx < 1 || cfg->ny < 1) return fail(CLBM_EINVAL, "nx and ny must be >= 1");
     const int eb = elem_bytes(cfg->storage);
-    if (eb && pitch_of(cfg->nx) * rows_allocated(cfg->nx, cfg->ny, eb) > (int64_t)INT32_MAX)
+    if (eb && pitch_of(cfg->nx, eb) * rows_allocated(cfg->nx, cfg->ny, eb) > (int64_t)INT32_MAX)
         return fail(CLBM_EINVAL, "lattice too large (nx * ny must stay below 2^31)");
     if (cfg->bc_y != CLBM_Y_PERIODIC && cfg->bc_y != CLBM_Y_BOUNCEBACK)
         return fail(CLBM_EINVAL, "bc_y must be CLBM_Y_PERIODIC or CLBM_Y_BOUNCEBACK");
@@ -379,7 +379,7 @@ int clbm_create(const clbm_config *cfg, clbm_handle **out)
     d.buf[1] = inplace ? cfg->pop_a : cfg->pop_b;
     d.inplace = inplace ? 1 : 0;
     d.rshift = row_shift(cfg->nx, cfg->ny, eb);
-    d.pitch = pitch_of(cfg->nx);
+    d.pitch = pitch_of(cfg->nx, eb);
     d.dstride = d.pitch << d.rshift;
     d.bstride = 9 * d.dstride;
     d.nx = cfg->nx;
@@ -521,7 +521,7 @@ int clbm_step(clbm_handle *h, int64_t nsteps)
     if (rc) return rc;
     if (nsteps < 0) return fail(CLBM_EINVAL, "nsteps must be >= 0");
     const int rvec = h->d.storage == CLBM_F64 ? 2 : 4;
-    const int64_t groups = (int64_t)h->d.ny * (pitch_of(h->d.nx) / rvec);
+    const int64_t groups = (int64_t)h->d.ny * (h->d.pitch / rvec);
     if (nsteps >= 2 && h->d.force_mode != clbm::FM_SC && groups <= h->resident_max) {
         // A small lattice: many steps per launch in one resident block.
         for (int64_t left = nsteps; left > 0;) {
@@ -833,7 +833,7 @@ void batch_geometry(clbm_batch *b)
         size_t bytes = 0, largest = 0;
         while (pos < b->order.size() && group_key(b->lats[b->order[pos]]) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
-            clbm::tile_geometry(d.nx, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
+            clbm::tile_geometry(d.pitch, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
             if (pairs)  // tiles of the two-step kernel in the variant's shape
                 d.ntiles = (int64_t)((d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape)) *
                            ((d.ny + clbm::tile_h(shape) - 1) / clbm::tile_h(shape));

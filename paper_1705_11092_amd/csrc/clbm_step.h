@@ -368,7 +368,7 @@ hipError_t step_dispatch(const LatDesc &d, int src, size_t lds, hipStream_t s)
 {
     LatDesc e = d;
     int64_t ntiles;
-    tile_geometry(d.nx, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
+    tile_geometry(d.pitch, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
     e.vec = VEC;
     const dim3 grid((unsigned)ntiles), block(kBlock);
     switch (kernel_key(d)) {
@@ -416,7 +416,7 @@ hipError_t resident_dispatch(const LatDesc &d, int src, int nsteps, hipStream_t 
 {
     LatDesc e = d;
     int64_t ntiles;
-    tile_geometry(d.nx, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
+    tile_geometry(d.pitch, d.ny, VEC, &e.tpr, &e.inv_tpr, &ntiles);
     e.vec = VEC;
     switch (kernel_key(d)) {
         CLBM_FOR_SCHEMES(CLBM_RESIDENT_CASE, FM_CONST, false)

@@ -2,8 +2,9 @@
 // (pull) form.  Included by the translation units of the storage types that
 // use it, after clbm_step.h.
 //
-// One block owns a tile of TH rows x TW columns (64 x 16 or 32 x 32, 256
-// threads, 4 nodes per thread in phase B).  Phase A collides step n + 1 on
+// One block owns a tile of TH rows x TW columns (256 threads, NPT nodes per
+// thread in phase B: 64 x 16 or 32 x 32 with 4, or, for FP64, 32 x 16 with
+// 2, whose LDS lets four blocks share a compute unit instead of two).  Phase A collides step n + 1 on
 // the tile's region: the tile's nodes that lie in the lattice and a one-node
 // halo around them (the nodes whose post-collision values step n + 2 of the
 // tile pulls, Eq. 10), reading the state of step n from HBM, and keeps the
@@ -18,7 +19,7 @@
 // post-collision slot i of node (r - e_y,i, c - e_x,i), or, where that node
 // lies beyond a wall, the node's own post-collision slot opp(i) (half-way
 // bounce-back), which phase A writes there in place of the absent node.
-// Phase B thus reads four consecutive nodes of a slot as one aligned vector.
+// Phase B thus reads NPT consecutive nodes of a slot as one aligned vector.
 #pragma once
 
 #include <type_traits>
@@ -29,18 +30,23 @@ namespace clbm {
 
 namespace {
 
-template <int TW_, int TH_>
+template <int TW_, int TH_, int NPT_ = 4>
 struct Tile {
     static constexpr int TW = TW_, TH = TH_;           // tile: columns x rows
+    static constexpr int NPT = NPT_;                   // phase-B nodes per thread (even)
     static constexpr int RW = TW + 2, RH = TH + 2;     // the tile with its one-node halo
-    static constexpr int LPR = TW / 4;                 // phase-B threads per tile row
-    static_assert(TW * TH == 4 * kBlock, "phase B: 4 nodes per thread");
+    static constexpr int LPR = TW / NPT;               // phase-B threads per tile row
+    static_assert(TW * TH == NPT * kBlock && NPT % 2 == 0, "phase B: NPT nodes per thread, in pairs");
     static_assert(RH <= 64 && 64 + RW <= kBlock, "table fill: rows by wave 0, columns from thread 64");
 };
 using T64x16 = Tile<64, 16>;
 using T32x32 = Tile<32, 32>;
+using T32x16 = Tile<32, 16, 2>;
 
-constexpr int kStripTiles = 8;  // tile columns per strip of the tile walk
+// Nodes across a strip of the tile walk (8 tiles of 64 columns, 16 of 32).
+// Measured on FP64 4096^2 with 32 x 16 tiles: strips of 128, 256, 512 and
+// 1024 nodes gave 48, 56, 81 and 81 GLUPS.
+constexpr int kStripNodes = 512;
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {
@@ -132,11 +138,12 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     // Phase B's nodes and their force, read first: a table-driven force
     // (Kolmogorov rows, a field) then arrives during phase A instead of
     // adding a memory round trip to phase B.
-    const int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * 4;
+    constexpr int NPT = TL::NPT;
+    const int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * NPT;
     const int yb = y0 + rb < d.ny ? y0 + rb : d.ny - 1;
-    R FxB[4], FyB[4];
+    R FxB[NPT], FyB[NPT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) force_at<R, FM>(d, x0 + cb + k < d.nx ? x0 + cb + k : d.nx - 1, yb, FxB[k], FyB[k]);
+    for (int k = 0; k < NPT; ++k) force_at<R, FM>(d, x0 + cb + k < d.nx ? x0 + cb + k : d.nx - 1, yb, FxB[k], FyB[k]);
     // The tables: region row rr is lattice row y0 - 1 + rr, region column cc
     // lattice column x0 - 1 + cc, both periodic (a lattice narrower or lower
     // than the region repeats); a row beyond a wall is marked and takes the
@@ -268,33 +275,33 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     }
     __syncthreads();
 
-    // Phase B: 4 consecutive nodes per thread, node (x0 + c + k, y0 + r);
-    // slot i of all four is one aligned vector of LDS.
+    // Phase B: NPT consecutive nodes per thread, node (x0 + c + k, y0 + r);
+    // slot i of all of them is one aligned vector of LDS.
     const int r = rb, c = cb;
     const int y = y0 + r;
     if (y >= d.ny || x0 + c >= d.nx) return;
-    R g[4][9];
+    R g[NPT][9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const typename VecTypes<T, 4>::tight v = *reinterpret_cast<const typename VecTypes<T, 4>::tight *>(&lds[i][r][c]);
+        const typename VecTypes<T, NPT>::tight v = *reinterpret_cast<const typename VecTypes<T, NPT>::tight *>(&lds[i][r][c]);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g[k][i] = S::to_r(v[k]);
+        for (int k = 0; k < NPT; ++k) g[k][i] = S::to_r(v[k]);
     }
-    Pack<T, 4> q[9];
+    Pack<T, NPT> q[9];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) collide<R, SCH>(g[k], FxB[k], FyB[k], rt);
+    for (int k = 0; k < NPT; ++k) collide<R, SCH>(g[k], FxB[k], FyB[k], rt);
     if constexpr (S::kDither) {
-        // The one-step kernel's stochastic rounding of four nodes, in pairs.
-        uint32_t h[4];
+        // The one-step kernel's stochastic rounding of the nodes, in pairs.
+        uint32_t h[NPT];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NPT; ++k) {
             const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + c + k);
             h[k] = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
 #pragma unroll
-            for (int k = 0; k < 4; k += 2) {
+            for (int k = 0; k < NPT; k += 2) {
                 const auto two = S::from_r_sr2(g[k][i], sr_operand(h[k], i), g[k + 1][i], sr_operand(h[k + 1], i));
                 q[i].v[k] = two[0];
                 q[i].v[k + 1] = two[1];
@@ -302,14 +309,26 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 4; k += 2)
+        for (int k = 0; k < NPT; k += 2)
 #pragma unroll
             for (int i = 0; i < 9; ++i) round_pair<ST>(g[k][i], g[k + 1][i], &q[i].v[k]);
     }
     const I ob = row_at<I>(d, y) + (I)(x0 + c);
-    if (x0 + c + 4 <= d.nx) {
+    if (x0 + c + NPT <= d.nx) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) store_pack<T, 4, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+        for (int i = 0; i < 9; ++i) store_pack<T, NPT, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+        // NPT = 2: a row whose length leaves 1 or 2 in its last group of 4
+        // has that group's padding half written below.
+        if constexpr (NPT == 2) {
+            if (x0 + c + 2 == d.nx && (d.nx & 3)) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Pack<T, 2> pad;
+                    pad.v[0] = pad.v[1] = q[i].v[1];
+                    store_pack<T, 2, true>(elem<I>(out, ob + (I)2 + (I)i * (I)d.dstride), pad);
+                }
+            }
+        }
     } else {
         // The row's last group: real nodes, then copies of the last one in
         // the padding up to the next multiple of 4, so the row's cache
@@ -318,9 +337,17 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
 #pragma unroll
-            for (int k = 1; k < 4; ++k)
+            for (int k = 1; k < NPT; ++k)
                 if (k > kl) q[i].v[k] = q[i].v[k - 1];
-            store_pack<T, 4, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+            store_pack<T, NPT, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+            if constexpr (NPT == 2) {
+                // The last group of 4 ends 2 further on.
+                if ((x0 + c) % 4 == 0) {
+                    Pack<T, 2> pad;
+                    pad.v[0] = pad.v[1] = q[i].v[1];
+                    store_pack<T, 2, true>(elem<I>(out, ob + (I)2 + (I)i * (I)d.dstride), pad);
+                }
+            }
         }
     }
 }
@@ -373,7 +400,8 @@ __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, in
     const int left = d.steps - 2 * pair;
     const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
     int tx, ty;
-    strip_tile((int)lt, tiles_x, tiles_y, tiles_x < kStripTiles ? tiles_x : kStripTiles, tx, ty);
+    constexpr int kSw = kStripNodes / TL::TW;
+    strip_tile((int)lt, tiles_x, tiles_y, tiles_x < kSw ? tiles_x : kSw, tx, ty);
     const int x0 = tx * TL::TW, y0 = ty * TL::TH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
@@ -431,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ 
 template <int ST>
 hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
 {
-    using TL = T64x16;
+    using TL = std::conditional_t<ST == ST_F64, T32x16, T64x16>;
     const int64_t tiles = (int64_t)((d.nx + TL::TW - 1) / TL::TW) * ((d.ny + TL::TH - 1) / TL::TH);
     const dim3 grid((unsigned)tiles), block(kBlock);
     // Elements of one buffer: whole row blocks of bstride elements.
@@ -439,7 +467,8 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
     const int64_t elems = (d.ny + rows - 1) / rows * d.bstride;
     const bool small = elems * (int64_t)sizeof(typename Storage<ST>::T) + 4096 < ((int64_t)1 << 32);
     const int tiles_x = (d.nx + TL::TW - 1) / TL::TW;
-    const int sw = tiles_x < kStripTiles ? tiles_x : kStripTiles;
+    constexpr int kSw = kStripNodes / TL::TW;
+    const int sw = tiles_x < kSw ? tiles_x : kSw;
     switch (d.force_mode * 2 + d.scheme) {
 #define CLBM_S2(FM, SCH)                                                              \
     case FM * 2 + SCH:                                                                \

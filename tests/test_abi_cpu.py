@@ -31,7 +31,9 @@ def test_host_helpers():
     assert clbm.nonslip_s3(1.0) == pytest.approx(8.0 / 7.0)
     assert clbm.nonslip_s3(1.754) == pytest.approx(inputs.nonslip_s3(1.754))
     assert clbm.s_from_nu(0.01) == pytest.approx(1.0 / 0.53)
-    # Buffer sizes: 9 direction runs per row, each padded to 8 elements.
+    # Buffer sizes: 9 direction runs per row, each padded to 8 elements,
+    # or, for rows wider than 64 nodes, to a whole number of 128-byte lines
+    # (32 FP32, 16 FP64, 64 16-bit elements).
     G = 64  # spare bytes after the last row
     assert clbm.buffer_bytes(4096, 4096, "f32") == 9 * 4096 * 4096 * 4 + G
     assert clbm.buffer_bytes(4096, 4096, "f16") == 9 * 4096 * 4096 * 2 + G
@@ -40,13 +42,22 @@ def test_host_helpers():
     # Narrow lattices keep R = 2^k rows per block (runs of a direction in a
     # block reach 16 KB or R reaches the height), and ny rounds up to whole
     # blocks: 37 x 23 FP32 has 160-byte runs, R = 16, 32 rows allocated;
-    # 1030 x 9 has 4128-byte runs, R = 4, 12 rows; 1030 x 3 stops at R = 2
-    # (the height), 4 rows; 4100-wide FP32 rows exceed 16 KB, R = 1.
+    # 1030 x 9 has 4224-byte runs (1056 elements), R = 4, 12 rows; 1030 x 3
+    # stops at R = 2 (the height), 4 rows; 4100-wide FP32 rows (4128
+    # elements) exceed 16 KB, R = 1.
     assert clbm.buffer_bytes(37, 23, "f32") == 9 * 40 * 32 * 4 + G
     assert clbm.buffer_bytes(37, 16, "f32") == 9 * 40 * 16 * 4 + G
-    assert clbm.buffer_bytes(1030, 9, "f32") == 9 * 1032 * 12 * 4 + G
-    assert clbm.buffer_bytes(1030, 3, "f32") == 9 * 1032 * 4 * 4 + G
-    assert clbm.buffer_bytes(4100, 3, "f32") == 9 * 4104 * 3 * 4 + G
+    assert clbm.buffer_bytes(1030, 9, "f32") == 9 * 1056 * 12 * 4 + G
+    assert clbm.buffer_bytes(1030, 3, "f32") == 9 * 1056 * 4 * 4 + G
+    assert clbm.buffer_bytes(4100, 3, "f32") == 9 * 4128 * 3 * 4 + G
+    # The line padding starts above 64 nodes: 64 x 1 keeps 64 elements,
+    # 65 x 1 takes 96 (FP32), 80 (FP64) or 128 (16-bit) per run, and
+    # R = 2^k grows the rows as before (65 x 64 FP32: 384-byte runs, R = 64).
+    assert clbm.buffer_bytes(64, 1, "f32") == 9 * 64 * 1 * 4 + G
+    assert clbm.buffer_bytes(65, 1, "f32") == 9 * 96 * 1 * 4 + G
+    assert clbm.buffer_bytes(65, 1, "f64") == 9 * 80 * 1 * 8 + G
+    assert clbm.buffer_bytes(65, 1, "bf16") == 9 * 128 * 1 * 2 + G
+    assert clbm.buffer_bytes(65, 64, "f32") == 9 * 96 * 64 * 4 + G
     assert clbm.buffer_bytes(0, 5, "f32") == 0
     assert clbm.lib.clbm_buffer_bytes(5, 5, 9) == 0
     assert clbm.lib.clbm_buffer_bytes(5, 5, 6) == 0

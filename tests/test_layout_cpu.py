@@ -18,14 +18,16 @@ EB = {"f64": 8, "f32": 4, "f16": 2}
 VECS = {"f64": (2, 1), "f32": (4, 2, 1), "f16": (8, 4, 2)}
 
 
-def _pitch(nx):
-    return (nx + 7) // 8 * 8
+def _pitch(nx, eb):
+    # Runs padded to 8 elements, or, above 64 nodes, to 128-byte lines.
+    a = max(8, 128 // eb) if nx > 64 else 8
+    return (nx + a - 1) // a * a
 
 
 def _row_shift(nx, ny, eb):
     # Rows per block R = 2^k: runs of one direction in a block reach 16 KB,
     # or R reaches the height.
-    run, sh = _pitch(nx) * eb, 0
+    run, sh = _pitch(nx, eb) * eb, 0
     while (run << sh) < 16384 and (2 << sh) <= ny:
         sh += 1
     return sh
@@ -33,7 +35,7 @@ def _row_shift(nx, ny, eb):
 
 def _check(nx, ny, storage, vec, bc, inplace, buffer_bytes):
     eb = EB[storage]
-    P, rs = _pitch(nx), _row_shift(nx, ny, eb)
+    P, rs = _pitch(nx, eb), _row_shift(nx, ny, eb)
     R = 1 << rs
     rows = (ny + R - 1) // R * R
     total = buffer_bytes // eb

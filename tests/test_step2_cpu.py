@@ -1,24 +1,26 @@
 """Host-side checks of the two-step kernel's index maps (no GPU).
 
-The two-step kernel walks its tiles (64 x 16 or 32 x 32 nodes) in vertical
-strips of up to 8 tile columns, collides step n + 1 on each tile's region
-(the tile's nodes inside the lattice and a one-node halo: at most 66 x 18 or
-34 x 34 nodes, less for a tile at the lattice's right or lower edge) and
+The two-step kernel walks its tiles (64 x 16 or 32 x 32 nodes with 4 per
+thread in phase B, or, for FP64, 32 x 16 with 2) in vertical strips of up to
+512 nodes across, collides step n + 1 on each tile's region (the tile's
+nodes inside the lattice and a one-node halo: at most 66 x 18, 34 x 34 or
+34 x 18 nodes, less for a tile at the lattice's right or lower edge) and
 writes slot i of a region node straight into the LDS entry of the tile node
 that pulls it (Eq. 10), or, next to a bounce-back wall, the node's own
 reversed slot into the entry its absent neighbour would fill.  These tests
 restate that arithmetic and check that the walk visits every tile once,
 that every LDS entry phase B reads is written exactly once, by the source
-the pull with half-way bounce-back names, and that the region row of a
-region node comes out exact from its float product.
+the pull with half-way bounce-back names, that the region row of a region
+node comes out exact from its float product, and that phase B's stores
+cover each row and its padding up to the next multiple of 4 exactly once.
 """
 import pytest
 
 EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
 OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
-STRIP = 8
-SHAPES = [(64, 16), (32, 32)]
+STRIP_NODES = 512
+SHAPES = [(64, 16), (32, 32), (32, 16)]
 TW, TH = 64, 16
 
 
@@ -34,11 +36,12 @@ def strip_tile(t, tiles_x, tiles_y, sw):
     return full * sw + c, ty
 
 
+@pytest.mark.parametrize("tw,th", SHAPES)
 @pytest.mark.parametrize("nx,ny", [(1, 1), (64, 16), (65, 17), (300, 70), (1030, 9), (4096, 64),
                                    (520, 200), (64 * 13, 16 * 5)])
-def test_strip_walk_visits_every_tile_once(nx, ny):
-    tiles_x, tiles_y = (nx + TW - 1) // TW, (ny + TH - 1) // TH
-    sw = min(tiles_x, STRIP)
+def test_strip_walk_visits_every_tile_once(nx, ny, tw, th):
+    tiles_x, tiles_y = (nx + tw - 1) // tw, (ny + th - 1) // th
+    sw = min(tiles_x, STRIP_NODES // tw)
     seen = [strip_tile(t, tiles_x, tiles_y, sw) for t in range(tiles_x * tiles_y)]
     assert sorted(seen) == sorted((x, y) for x in range(tiles_x) for y in range(tiles_y))
     # Within a full strip the tile above is sw tiles earlier.
@@ -120,3 +123,25 @@ def test_region_row_from_float_product_is_exact(tw, th):
             j = np.arange(min(n, 5 * 256), dtype=np.int64)
             rr = ((j.astype(np.float32) + np.float32(0.5)) * inv).astype(np.int64)
             assert np.array_equal(rr, j // rw), (rw, rh)
+
+
+@pytest.mark.parametrize("npt", [4, 2])
+def test_phase_b_stores_cover_each_row_and_its_padding_once(npt):
+    # Phase B: the thread with nodes [c, c + npt) of a row stores them when
+    # c < nx, with copies of the last real node past nx; with npt = 2 the
+    # thread that holds the row's last node also fills the rest of its
+    # group of 4 (a second store of 2 at c + 2).
+    for nx in range(1, 80):
+        tw = 64 if npt == 4 else 32
+        written = []
+        for x0 in range(0, nx, tw):
+            for c in range(0, tw, npt):
+                if x0 + c >= nx:
+                    continue
+                written += range(x0 + c, x0 + c + npt)
+                if npt == 2:
+                    full = x0 + c + npt <= nx
+                    if (full and x0 + c + 2 == nx and nx % 4) or (not full and (x0 + c) % 4 == 0):
+                        written += range(x0 + c + 2, x0 + c + 4)
+        want = list(range((nx + 3) // 4 * 4))
+        assert sorted(written) == want, (npt, nx)
