@@ -177,10 +177,12 @@ def run_small():
     return out
 
 
-def run_batch(steps: int, warmup: int, count: int = 256):
+def run_batch(steps: int, warmup: int, count: int = 256, variant: int = -1, reps: int = 3):
     """The batch of uneven Kolmogorov lattices (sides log-uniform in
     [32, 512], seed 0), FP32 storage, two fused steps per launch over all
-    lattices (hbm_frac: 72 B per node per launch, i.e. per two updates)."""
+    lattices (hbm_frac: 72 B per node per launch, i.e. per two updates).
+    The kernel variant is the autotuner's, or `variant` when >= 0 (a
+    profiler's counters would distort the autotuner's timings)."""
     import torch
     from paper_1705_11092_amd import clbm, inputs
 
@@ -188,15 +190,23 @@ def run_batch(steps: int, warmup: int, count: int = 256):
     lats = [clbm.lattice_from_workload(wl, storage="f32") for wl in wls]
     b = clbm.Batch(lats)
     per_launch = 2 if lats[0].step_pairs else 1
-    variant = b.autotune(None)
+    if variant >= 0:
+        b.variant = variant
+    else:
+        variant = b.autotune(None)
     b.step(warmup)
     torch.cuda.synchronize()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(b.stream)
-    b.step(steps)
-    t1.record(b.stream)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
+    # The median of `reps` repetitions of `steps` steps (HIP events on the
+    # batch's stream).
+    times = []
+    for _ in range(reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(b.stream)
+        b.step(steps)
+        t1.record(b.stream)
+        torch.cuda.synchronize()
+        times.append(t0.elapsed_time(t1))
+    ms = sorted(times)[len(times) // 2]
     nodes = sum(wl.nx * wl.ny for wl in wls)
     b.close()
     for lat in lats:
@@ -205,7 +215,8 @@ def run_batch(steps: int, warmup: int, count: int = 256):
     mlups = nodes * steps / (ms / 1e3) / 1e6
     return {"workload": f"{count} Kolmogorov lattices, sides log-uniform 32..512 (seed 0), f32",
             "nodes": nodes, "steps": steps, "ms_per_step": round(ms / steps, 5),
-            "mlups": round(mlups, 1), "steps_per_launch": per_launch,
+            "mlups": round(mlups, 1), "repetitions": reps, "statistic": "median",
+            "steps_per_launch": per_launch,
             "hbm_frac": round(mlups * 1e6 * 72 / per_launch / 8e12, 4),
             "variant": variant}
 
@@ -382,6 +393,8 @@ def main():
                     help="timed repetitions of the headline (default: at least 5 and 400 steps)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 256-lattice batch leg (for profiling it)")
+    ap.add_argument("--batch-variant", type=int, default=-1,
+                    help="with --batch-only: this kernel variant instead of the autotuner's")
     args = ap.parse_args()
 
     if args.traffic_summary:
@@ -405,7 +418,8 @@ def main():
     # repetition reported (at least 5 repetitions and 400 timed steps).
     reps = args.reps or max(5, -(-400 // max(args.steps, 1)))
     if args.batch_only:
-        print(json.dumps(run_batch(max(args.steps, 2), args.warmup)), flush=True)
+        print(json.dumps(run_batch(max(args.steps, 2), args.warmup, variant=args.batch_variant, reps=1)),
+              flush=True)
         return
 
     ms, wall, tot = run_gpu(args.n, args.storage, args.steps, args.warmup, pairs=not args.single_steps,
@@ -497,7 +511,7 @@ def main():
                 extra[f"{st}_one_step_per_launch"] = {
                     "mlups": round(m1, 1), "ms_per_step": round(ms1 / args.steps, 5),
                     "hbm_frac": round(m1 * 1e6 * BYTES_PER_LUP[st] / 8e12, 4)}
-        extra["batch"] = run_batch(1000, 20)
+        extra["batch"] = run_batch(1000, 200)
         extra.update(run_small())
         if args.serve_requests > 0:
             extra["served"] = run_served(args.serve_requests)

@@ -3,8 +3,8 @@
 // use it, after clbm_step.h.
 //
 // One block owns a tile of TH rows x TW columns (256 threads, NPT nodes per
-// thread in phase B: 64 x 16 or 32 x 32 with 4, or, for FP64, 32 x 16 with
-// 2, whose LDS lets four blocks share a compute unit instead of two).  Phase A collides step n + 1 on
+// thread in phase B: 64 x 16 or 32 x 32 with 4, or, for FP64, 64 x 8 with 2,
+// whose LDS lets four blocks share a compute unit instead of two).  Phase A collides step n + 1 on
 // the tile's region: the tile's nodes that lie in the lattice and a one-node
 // halo around them (the nodes whose post-collision values step n + 2 of the
 // tile pulls, Eq. 10), reading the state of step n from HBM, and keeps the
@@ -41,7 +41,7 @@ struct Tile {
 };
 using T64x16 = Tile<64, 16>;
 using T32x32 = Tile<32, 32>;
-using T32x16 = Tile<32, 16, 2>;
+using T64x8 = Tile<64, 8, 2>;
 
 // Nodes across a strip of the tile walk (8 tiles of 64 columns, 16 of 32).
 // Measured on FP64 4096^2 with 32 x 16 tiles: strips of 128, 256, 512 and
@@ -459,7 +459,13 @@ __global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ 
 template <int ST>
 hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
 {
-    using TL = std::conditional_t<ST == ST_F64, T32x16, T64x16>;
+    // FP64: 64 x 8 tiles with 2 nodes per thread in phase B.  Their 37 KB
+    // of LDS let four blocks share a compute unit where the 74 KB of a
+    // 64 x 16 tile let two: 4096^2 went from 70 to 84 GLUPS (32 x 16 tiles:
+    // 81), though they collide more halo (66 x 10 region nodes per 512).
+    // FP32 and 16-bit storage keep 64 x 16 (with 32 x 16 FP32 lost 3 %, FP16
+    // 13 %).
+    using TL = std::conditional_t<ST == ST_F64, T64x8, T64x16>;
     const int64_t tiles = (int64_t)((d.nx + TL::TW - 1) / TL::TW) * ((d.ny + TL::TH - 1) / TL::TH);
     const dim3 grid((unsigned)tiles), block(kBlock);
     // Elements of one buffer: whole row blocks of bstride elements.

@@ -1,10 +1,10 @@
 """Host-side checks of the two-step kernel's index maps (no GPU).
 
 The two-step kernel walks its tiles (64 x 16 or 32 x 32 nodes with 4 per
-thread in phase B, or, for FP64, 32 x 16 with 2) in vertical strips of up to
+thread in phase B, or, for FP64, 64 x 8 with 2) in vertical strips of up to
 512 nodes across, collides step n + 1 on each tile's region (the tile's
 nodes inside the lattice and a one-node halo: at most 66 x 18, 34 x 34 or
-34 x 18 nodes, less for a tile at the lattice's right or lower edge) and
+66 x 10 nodes, less for a tile at the lattice's right or lower edge) and
 writes slot i of a region node straight into the LDS entry of the tile node
 that pulls it (Eq. 10), or, next to a bounce-back wall, the node's own
 reversed slot into the entry its absent neighbour would fill.  These tests
@@ -20,7 +20,7 @@ EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
 OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
 STRIP_NODES = 512
-SHAPES = [(64, 16), (32, 32), (32, 16)]
+SHAPES = [(64, 16), (32, 32), (64, 8)]
 TW, TH = 64, 16
 
 
@@ -125,14 +125,13 @@ def test_region_row_from_float_product_is_exact(tw, th):
             assert np.array_equal(rr, j // rw), (rw, rh)
 
 
-@pytest.mark.parametrize("npt", [4, 2])
-def test_phase_b_stores_cover_each_row_and_its_padding_once(npt):
+@pytest.mark.parametrize("npt,tw", [(4, 64), (4, 32), (2, 64), (2, 32)])
+def test_phase_b_stores_cover_each_row_and_its_padding_once(npt, tw):
     # Phase B: the thread with nodes [c, c + npt) of a row stores them when
     # c < nx, with copies of the last real node past nx; with npt = 2 the
     # thread that holds the row's last node also fills the rest of its
     # group of 4 (a second store of 2 at c + 2).
-    for nx in range(1, 80):
-        tw = 64 if npt == 4 else 32
+    for nx in range(1, 140):
         written = []
         for x0 in range(0, nx, tw):
             for c in range(0, tw, npt):
