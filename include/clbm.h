@@ -185,8 +185,7 @@ int clbm_init(clbm_handle *h, const double *rho, const double *ux, const double 
  * the back-transform of Eq. (9), then streaming (Eq. 10), fused in one
  * kernel launch per step (two buffers: each node gathers its pre-collision
  * populations from its neighbours' post-collision ones; in place: the AA
- * pattern of clbm_streaming).  Two-buffer FP32 and 16-bit lattices and FP64
- * lattices of at least 128 tiles of 64 x 16 nodes (any force but
+ * pattern of clbm_streaming).  Two-buffer lattices (any force but
  * Shan-Chen) advance two steps per launch by default (clbm_set_step_pairs),
  * with bitwise the same result.  Long runs replay a captured hipGraph.
  * Errors: CLBM_ESTATE before clbm_init or clbm_set_populations, CLBM_EINVAL
@@ -259,15 +258,15 @@ int clbm_set_graph_steps(clbm_handle *h, int32_t steps);
 int clbm_set_occupancy(clbm_handle *h, int32_t blocks_per_cu);
 
 /* Two fused steps per launch (enable = 1) or one (0), or the default (-1).  A block
- * computes step n + 1 on a 64 x 16 tile and a one-node halo from HBM, keeps
- * it in LDS, and computes step n + 2 from there, so the state crosses HBM
+ * computes step n + 1 on a tile (64 x 16 nodes, 64 x 8 for FP64) and a
+ * one-node halo from HBM, keeps it in LDS, and computes step n + 2 from
+ * there, so the state crosses HBM
  * once per two steps; every node update is the one-step kernel's, so results
  * are bitwise equal either way (stochastic rounding included: a node's
  * operand depends on its index and values only).  Applies to two-buffer
  * lattices of every storage type without the Shan-Chen force; in-place
  * lattices always step singly.  The default, from measurements on MI355X:
- * pairs for FP32 and the 16-bit types at every size, for FP64 from 128
- * tiles (smaller FP64 lattices step faster singly).  clbm_get_step_pairs
+ * pairs for every storage type at every size.  clbm_get_step_pairs
  * returns 1 when this lattice steps in pairs, 0 when not, -1 for NULL.
  * Errors: CLBM_EINVAL (NULL handle, enable not -1, 0 or 1). */
 int clbm_set_step_pairs(clbm_handle *h, int32_t enable);

@@ -238,7 +238,7 @@ class Lattice:
     @step_pairs.setter
     def step_pairs(self, enable: Optional[bool]):
         """True: pairs wherever supported; False: never; None: the default
-        (FP32 and 16-bit always, FP64 from 128 tiles of 64 x 16 nodes)."""
+        (pairs wherever supported)."""
         _check(lib.clbm_set_step_pairs(self._h, -1 if enable is None else (1 if enable else 0)))
 
     @property

@@ -278,18 +278,11 @@ void drop_graphs(clbm_handle *h)
 size_t step_lds(const clbm_handle *h, int src) { return h->d.inplace && src == 0 ? h->lds0 : h->lds; }
 
 // Whether steps go two per launch (the fused two-step kernel).
-// Measured on MI355X, graphed steps: FP32 and 16-bit lattices step faster
-// in pairs at every size (64 x 32: FP32 3.6 against 4.3 us per step, FP16
-// 3.7 against 4.3, two launches becoming one); FP64 ones, whose two-step
-// blocks are fewer per CU and longer, only from 128 tiles of 64 x 16 nodes
-// (64 tiles: 4.7 against 4.3 us per step, 128: 5.0 against 5.2, 512: 8.8
-// against 14.3).
-bool pairs_by_default(const clbm::LatDesc &d)
-{
-    if (d.storage != CLBM_F64) return true;
-    const int64_t tiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + 15) / 16);
-    return tiles >= 128;
-}
+// Measured on MI355X, graphed steps: every storage type steps faster in
+// pairs at every size (64 x 32: FP32 3.6 against 4.3 us per step, FP16 3.7
+// against 4.3, two launches becoming one; FP64 in its 64 x 8 tiles: 96^2
+// 2.9 against 4.0, 256^2 3.2 against 4.4, 512^2 5.0 against 7.2).
+bool pairs_by_default(const clbm::LatDesc &) { return true; }
 
 bool use_pairs(const clbm_handle *h)
 {
@@ -836,7 +829,7 @@ void batch_geometry(clbm_batch *b)
             clbm::tile_geometry(d.pitch, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
             if (pairs)  // tiles of the two-step kernel in the variant's shape
                 d.ntiles = (int64_t)((d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape)) *
-                           ((d.ny + clbm::tile_h(shape) - 1) / clbm::tile_h(shape));
+                           ((d.ny + clbm::tile_h(shape, st) - 1) / clbm::tile_h(shape, st));
             d.vec = vec;
             d.pairs = pairs ? 1 : 0;
             d.tile0 = tiles;

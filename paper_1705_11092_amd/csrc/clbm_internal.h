@@ -118,10 +118,16 @@ inline void set_rates(LatDesc &d, double s1, double sb, double s2, double s3, do
 }
 
 // Tile shapes of the two-step kernels (columns x rows of nodes per block of
-// kBlock threads, 4 nodes per thread in its second step).
+// kBlock threads, 4 nodes per thread in its second step): 64 x 16 or 32 x
+// 32, for FP64 storage (whose LDS holds half as many nodes) 64 x 8 or 32 x
+// 16 with 2 nodes per thread.
 enum TileShape { kTile64x16 = 0, kTile32x32 = 1 };
 inline int tile_w(int shape) { return shape == kTile32x32 ? 32 : 64; }
-inline int tile_h(int shape) { return shape == kTile32x32 ? 32 : 16; }
+inline int tile_h(int shape, int storage)
+{
+    const int h = shape == kTile32x32 ? 32 : 16;
+    return storage == ST_F64 ? h / 2 : h;
+}
 
 // Lattice descriptors carried in one upload kernel's arguments.
 constexpr int kUploadMax = 12;

@@ -42,6 +42,7 @@ struct Tile {
 using T64x16 = Tile<64, 16>;
 using T32x32 = Tile<32, 32>;
 using T64x8 = Tile<64, 8, 2>;
+using T32x16 = Tile<32, 16, 2>;
 
 // Nodes across a strip of the tile walk (8 tiles of 64 columns, 16 of 32).
 // Measured on FP64 4096^2 with 32 x 16 tiles: strips of 128, 256, 512 and
@@ -407,8 +408,12 @@ __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, in
     if (left >= 2) {
         pair_tile<ST, FM, SCH, I, TL>(d, src, x0, y0, lds, tab);
     } else {
-        const int r = threadIdx.x / TL::LPR, c = (threadIdx.x % TL::LPR) * 4;
-        if (y0 + r < d.ny && x0 + c < d.nx) step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
+        // The one-step node update in groups of 4 (TW / 4 threads per tile
+        // row; with 2 nodes per thread in phase B only half the threads).
+        constexpr int kLpr = TL::TW / 4;
+        const int r = threadIdx.x / kLpr, c = (threadIdx.x % kLpr) * 4;
+        if (r < TL::TH && y0 + r < d.ny && x0 + c < d.nx)
+            step_group<ST, 4, FM, SCH, false>(d, src, y0 + r, x0 + c);
     }
 }
 
@@ -535,8 +540,13 @@ template <int ST>
 hipError_t launch_batch2_st(const LatDesc *lats, const int32_t *tile_lat, int64_t ntiles, int key, bool small,
                             int pair, int shape, int grid, hipStream_t s)
 {
-    if (shape == kTile32x32) return batch2_shape<ST, T32x32>(lats, tile_lat, ntiles, key, small, pair, grid, s);
-    return batch2_shape<ST, T64x16>(lats, tile_lat, ntiles, key, small, pair, grid, s);
+    // The shapes of tile_w and tile_h, which numbered the lattices' tiles.
+    constexpr bool f64 = ST == ST_F64;
+    if (shape == kTile32x32)
+        return batch2_shape<ST, std::conditional_t<f64, T32x16, T32x32>>(lats, tile_lat, ntiles, key, small, pair,
+                                                                         grid, s);
+    return batch2_shape<ST, std::conditional_t<f64, T64x8, T64x16>>(lats, tile_lat, ntiles, key, small, pair, grid,
+                                                                    s);
 }
 
 }  // namespace clbm

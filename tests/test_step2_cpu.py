@@ -20,7 +20,7 @@ EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
 OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
 STRIP_NODES = 512
-SHAPES = [(64, 16), (32, 32), (64, 8)]
+SHAPES = [(64, 16), (32, 32), (64, 8), (32, 16)]
 TW, TH = 64, 16
 
 
