@@ -290,7 +290,7 @@ def traffic_summary(dirs, copy_bytes: int = 603979776, n: int = 4096):
     step_args = "--steps 6 --warmup 0 --reps 1 --no-cpu-baseline --no-extra"
     copy_args = f"--calibrate-copy {copy_bytes}"
     out = {
-        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16>> (two fused steps per launch; FP32 "
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16, 4>> (two fused steps per launch; FP32 "
                   "deviations, constant force, consistent scheme, 64 x 16 tiles)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),
@@ -334,7 +334,7 @@ def valu_summary(d: str, n: int = 4096):
     waves = statistics.median(e["SQ_WAVES"] for e in per.values())
     clocks = [e["GRBM_GUI_ACTIVE"] / 8.0 / e["ns"] for e in per.values() if e.get("ns")]
     out = {
-        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16>> (two fused steps per launch; FP32 "
+        "kernel": "clbm::k_step2<1, 0, 0, unsigned int, Tile<64, 16, 4>> (two fused steps per launch; FP32 "
                   "deviations, constant force, consistent scheme, 64 x 16 tiles)",
         "workload": f"taylor_green_{n}x{n}_uniform_force", "storage": "f32", "nodes": n * n,
         "kernel_hash": kernel_hash(),
