@@ -409,7 +409,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
               "multi-GPU path; the lattice would be split into y-slabs with one halo "
               "exchange per step.", file=sys.stderr)
         sys.exit(2)
