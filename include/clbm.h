@@ -324,8 +324,9 @@ int clbm_batch_step_each(clbm_batch *b, const int64_t *nsteps);
  * fastest (results do not depend on the variant).  A variant has two parts:
  * one for the lattices that step one step per launch (bytes per thread per
  * direction, occupancy cap, persistent grid) and one for those that step
- * in fused pairs (tile shape 64 x 16 or 32 x 32 nodes, one block per tile or
- * persistent blocks walking the tiles).  The first part is chosen on the
+ * in fused pairs (tile shape 64 x 16 or 32 x 32 nodes -- half as many rows
+ * for FP64 -- or per lattice whichever of the two covers it with fewer
+ * tiles; one block per tile or persistent blocks walking the tiles).  The first part is chosen on the
  * lattices that step singly, timing one step of each, then the second on
  * those that step in pairs, timing one fused pair of each.  With cache_path
  * set, look the choice up first and record it after, keyed by architecture,

@@ -727,15 +727,17 @@ const Variant kVariants[] = {
     {8, 0, 0},   {8, 16, 0}, {4, 0, -1}, {4, 0, 0},  {4, 16, 0},
 };
 constexpr int kNumSingle = sizeof(kVariants) / sizeof(kVariants[0]);
-// Two-step variants: the tile shape (64 x 16 or 32 x 32 nodes) and the grid
+// Two-step variants: the tile shape (64 x 16 or 32 x 32 nodes, or, per
+// lattice, whichever of the two gives it fewer tiles) and the grid
 // (persistent blocks per compute unit walking the tiles, or 0: one block per
 // tile; the two-step kernel's LDS lets 4 blocks share a compute unit).
+constexpr int kShapePerLattice = 2;
 struct PairVariant {
     int shape;
     int blocks_per_cu;
 };
-const PairVariant kPairVariants[] = {
-    {clbm::kTile64x16, 0}, {clbm::kTile32x32, 0}, {clbm::kTile64x16, 4}, {clbm::kTile32x32, 4}};
+const PairVariant kPairVariants[] = {{clbm::kTile64x16, 0}, {clbm::kTile32x32, 0}, {clbm::kTile64x16, 4},
+                                     {clbm::kTile32x32, 4}, {kShapePerLattice, 0}};
 constexpr int kNumPair = sizeof(kPairVariants) / sizeof(kPairVariants[0]);
 constexpr int kNumVariants = kNumSingle * kNumPair;
 int single_index(int v) { return v / kNumPair; }
@@ -770,7 +772,8 @@ struct clbm_batch {
         int64_t ntiles;
         int64_t tbase;                // first entry of the group in the tile map
         size_t lds;                   // dynamic LDS per block enforcing the cap
-        bool pairs;                   // two fused steps per launch (64 x 16 tiles)
+        bool pairs;                   // two fused steps per launch
+        int shape;                    // pairs: the tile shape (clbm::TileShape)
         bool small;                   // pairs: every buffer below 4 GB
     };
     std::vector<Group> groups;
@@ -786,23 +789,39 @@ struct clbm_batch {
 
 namespace {
 
-// Launch group of a lattice: whether it steps in pairs, storage type and
-// kernel (storage scheme, force mode, forcing scheme).
-int group_key(const clbm_handle *h)
+// Tile shape of a lattice stepping in pairs under the two-step variant's
+// shape: the variant's, or the one of 64 x 16 and 32 x 32 that covers the
+// lattice with fewer tiles (64 x 16 on a tie).
+int pair_shape(int variant_shape, const clbm::LatDesc &d)
 {
-    return ((use_pairs(h) ? 1 : 0) * kStorageKinds + h->d.storage) * clbm::kKernelKeys + clbm::kernel_key(h->d);
+    if (variant_shape != kShapePerLattice) return variant_shape;
+    auto tiles = [&](int shape) {
+        const int w = clbm::tile_w(shape), h = clbm::tile_h(shape, d.storage);
+        return (int64_t)((d.nx + w - 1) / w) * ((d.ny + h - 1) / h);
+    };
+    return tiles(clbm::kTile32x32) < tiles(clbm::kTile64x16) ? clbm::kTile32x32 : clbm::kTile64x16;
 }
 
-// Table order: grouped by storage and kernel (one launch per group), caller
-// order inside a group.
+// Launch group of a lattice: whether it steps in pairs and in which tile
+// shape, storage type and kernel (storage scheme, force mode, forcing
+// scheme).
+constexpr int kGroupKeys = 3 * kStorageKinds * clbm::kKernelKeys;
+int group_key(const clbm_batch *b, const clbm_handle *h)
+{
+    const int cls = use_pairs(h) ? 1 + pair_shape(pair_of(b->variant).shape, h->d) : 0;
+    return (cls * kStorageKinds + h->d.storage) * clbm::kKernelKeys + clbm::kernel_key(h->d);
+}
+
+// Table order: grouped by tile shape, storage and kernel (one launch per
+// group), caller order inside a group.
 void batch_order(clbm_batch *b)
 {
     b->order.clear();
     b->keys.clear();
-    for (int key = 0; key < 2 * kStorageKinds * clbm::kKernelKeys; ++key)
+    for (auto *h : b->lats) b->keys.push_back(group_key(b, h));
+    for (int key = 0; key < kGroupKeys; ++key)
         for (size_t j = 0; j < b->lats.size(); ++j)
-            if (group_key(b->lats[j]) == key) b->order.push_back((int)j);
-    for (auto *h : b->lats) b->keys.push_back(group_key(h));
+            if (b->keys[j] == key) b->order.push_back((int)j);
 }
 
 // Geometry of the current variant: per lattice nodes per thread, tile
@@ -816,18 +835,18 @@ void batch_geometry(clbm_batch *b)
     while (pos < b->order.size()) {
         const clbm_handle *h0 = b->lats[b->order[pos]];
         const LatDesc &d0 = h0->d;
-        const int key = group_key(h0);
+        const int key = group_key(b, h0);
         const bool pairs = use_pairs(h0);
         const int st = d0.storage;
         const int vec = pairs ? 4 : vec_for(st, single_of(b->variant).vec_bytes);
-        const int shape = pair_of(b->variant).shape;
+        const int shape = pairs ? pair_shape(pair_of(b->variant).shape, d0) : clbm::kTile64x16;
         const int lo = (int)pos;
         int64_t tiles = 0;
         size_t bytes = 0, largest = 0;
-        while (pos < b->order.size() && group_key(b->lats[b->order[pos]]) == key) {
+        while (pos < b->order.size() && group_key(b, b->lats[b->order[pos]]) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
             clbm::tile_geometry(d.pitch, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
-            if (pairs)  // tiles of the two-step kernel in the variant's shape
+            if (pairs)  // tiles of the two-step kernel in the group's shape
                 d.ntiles = (int64_t)((d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape)) *
                            ((d.ny + clbm::tile_h(shape, st) - 1) / clbm::tile_h(shape, st));
             d.vec = vec;
@@ -843,7 +862,7 @@ void batch_geometry(clbm_batch *b)
         const int cap = single_of(b->variant).cap;
         const size_t lds = lds_for_occupancy(cap < 0 ? default_occupancy(st, bytes) : cap);
         const bool small = largest + 4096 < ((size_t)1 << 32);
-        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds, pairs, small});
+        b->groups.push_back({st, clbm::kernel_key(d0), vec, lo, (int)pos, tiles, tbase, lds, pairs, shape, small});
         tbase += tiles;
     }
     b->map_dirty = true;
@@ -905,7 +924,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *spare = nullptr)
 void batch_refresh(clbm_batch *b)
 {
     for (size_t j = 0; j < b->lats.size(); ++j) {
-        if (group_key(b->lats[j]) != b->keys[j]) {
+        if (group_key(b, b->lats[j]) != b->keys[j]) {
             batch_order(b);
             batch_geometry(b);
             return;
@@ -957,7 +976,7 @@ int batch_launch_steps(clbm_batch *b, int k0, int n, hipStream_t s, int which = 
             const int gg = (int)std::min<int64_t>(pgrid, g.ntiles);
             for (int p = k0 / 2; p < (k0 + n + 1) / 2; ++p)
                 HIPCHK(clbm::launch_batch2(g.storage, b->d_lats, b->d_tile_lat + g.tbase, g.ntiles, g.key,
-                                           g.small, p, pv.shape, gg, gs));
+                                           g.small, p, g.shape, gg, gs));
             continue;
         }
         const int gg = (int)std::min<int64_t>(grid, g.ntiles);
@@ -1114,6 +1133,7 @@ int clbm_batch_set_variant(clbm_batch *b, int32_t variant)
     if (variant < 0 || variant >= kNumVariants) return fail(CLBM_EINVAL, "variant out of range");
     if (variant == b->variant) return CLBM_OK;
     b->variant = variant;
+    batch_order(b);  // the groups of a per-lattice tile shape differ
     batch_geometry(b);
     return CLBM_OK;
 }

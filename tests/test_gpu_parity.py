@@ -200,9 +200,10 @@ def test_batch_pairs_equal_single_steps():
     more = [3, 2, 1, 4, 7, 0, 5, 3, 0]
     out = []
     # Singly, then in pairs with each two-step variant (tile shapes 64 x 16
-    # and 32 x 32, one block per tile or persistent blocks): variants
-    # 0 .. 3 share the single-step part and differ in the two-step part.
-    for pairs, variant in ((False, 0), (True, 0), (True, 1), (True, 2), (True, 3)):
+    # and 32 x 32, one block per tile or persistent blocks, and the shape
+    # chosen per lattice): variants 0 .. 4 share the single-step part and
+    # differ in the two-step part.
+    for pairs, variant in ((False, 0), (True, 0), (True, 1), (True, 2), (True, 3), (True, 4)):
         lats = []
         for k, (nx, ny, bc, force, storage, inplace) in enumerate(shapes):
             wl = inputs.random_state(nx, ny, seed=970 + k, bc_y=bc, force=force, amp_f=1e-3,
