@@ -3,13 +3,13 @@
 // use it, after clbm_step.h.
 //
 // One block owns a tile of TH rows x TW columns (256 threads, NPT nodes per
-// thread in phase B: 64 x 16 or 32 x 32 with 4, or, for FP64, 64 x 8 with 2,
-// whose LDS lets four blocks share a compute unit instead of two).  Phase A collides step n + 1 on
-// the tile's region: the tile's nodes that lie in the lattice and a one-node
-// halo around them (the nodes whose post-collision values step n + 2 of the
-// tile pulls, Eq. 10), reading the state of step n from HBM, and keeps the
-// results in LDS, rounded to the storage type exactly as the one-step kernel
-// would store them.  Phase B collides step n + 2 on the tile from LDS and
+// thread in phase B: 64 x 16 or 32 x 32 with 4, or, for FP64, 64 x 8 or
+// 32 x 16 with 2, whose LDS lets four blocks share a compute unit instead of
+// two).  Phase A collides step n + 1 on the tile's region: the tile's nodes
+// that lie in the lattice and a one-node halo around them (the nodes whose
+// post-collision values step n + 2 of the tile pulls, Eq. 10), reading the
+// state of step n from HBM, and keeps the results in LDS, rounded to the
+// storage type exactly as the one-step kernel would store them.  Phase B collides step n + 2 on the tile from LDS and
 // writes the other buffer.  The state thus crosses HBM once per two steps
 // (plus the halo's re-reads), and every node update is the one-step
 // kernel's, so the result is bitwise that of two one-step launches.
