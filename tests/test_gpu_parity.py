@@ -133,21 +133,35 @@ def test_taylor_green_1024_graph_path(storage):
     assert rel_l2(rg, ro) <= TOL_U[storage]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16sr", "bf16sr"])
-def test_taylor_green_4096_full_size(storage):
-    # The 4096^2 workload at full size in the bench's launch configuration,
-    # two steps, every node compared.
-    wl = inputs.taylor_green(4096, steps=2)
-    log(f"TG4096 {storage}: oracle ...")
+@pytest.fixture(scope="module")
+def tg4096_oracle():
+    # 24 steps of the 4096^2 workload on the oracle (a few seconds on the
+    # host's cores), shared by the storage types below.
+    wl = inputs.taylor_green(4096, steps=24)
+    log(f"TG4096: oracle, {wl.steps} steps ...")
     fo, ro, uo, vo = oracle_run(wl, wl.steps)
-    log("  gpu ...")
+    return wl, fo, ro, uo, vo
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "f16sr", "bf16sr"])
+def test_taylor_green_4096_full_size(storage, tg4096_oracle):
+    # The 4096^2 workload at full size in the bench's launch configuration
+    # (two fused steps per launch: 12 launches), every node compared; for
+    # FP64 every population too.
+    wl, fo, ro, uo, vo = tg4096_oracle
+    log(f"TG4096 {storage}: gpu ...")
     lat = gpu_lattice(wl, storage)
+    assert lat.step_pairs
     lat.step(wl.steps)
     rho, ux, uy, tot = lat.moments()
     e = e2_u(ux.cpu().numpy(), uy.cpu().numpy(), uo, vo)
     log(f"  E2(u) = {e:.3e}")
     assert e <= TOL_U[storage]
     assert abs(tot[0] - float(ro.sum())) / float(ro.sum()) < TOL_MASS[storage]
+    if storage == "f64":
+        d = float(np.max(np.abs(lat.get_populations().cpu().numpy() - fo)))
+        log(f"  max |f - f_oracle| = {d:.3e}")
+        assert d <= 1e-13
     lat.close()
 
 
