@@ -129,8 +129,9 @@ typedef struct {
 } clbm_config;
 
 /* Bytes each of pop_a and pop_b must hold for this lattice and storage:
- * 9 populations per node, each row padded to a multiple of 8 elements and
- * the height rounded up to whole row blocks (narrow lattices group up to
+ * 9 populations per node, each row padded to a multiple of 8 elements (of
+ * 128 bytes for rows wider than 64 nodes) and the height rounded up to
+ * whole row blocks (narrow lattices group up to
  * 2^k rows per block), plus 64 spare bytes at the end (the step's vector
  * loads may reach one element past the last row).  The layout inside is
  * the library's; use
