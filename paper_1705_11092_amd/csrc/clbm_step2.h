@@ -109,7 +109,7 @@ __device__ __forceinline__ I row_at(const LatDesc &d, int y)
 }
 
 // Two fused steps of the tile at (x0, y0) from buffer src into src ^ 1.
-template <int ST, int FM, int SCH, typename I, typename TL>
+template <int ST, int FM, int SCH, typename I, typename TL, bool PACK = false>
 __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int y0,
                                           typename Storage<ST>::T (&lds)[9][TL::TH][TL::TW],
                                           TileTabs<I, TL> &tab)
@@ -140,7 +140,18 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     // (Kolmogorov rows, a field) then arrives during phase A instead of
     // adding a memory round trip to phase B.
     constexpr int NPT = TL::NPT;
-    const int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * NPT;
+    int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * NPT;
+    if constexpr (PACK) {
+        // A tile at a lattice's right edge: phase B's threads packed onto
+        // the columns in the lattice, so that whole waves idle instead of
+        // every wave in part (the row from a float product, exact for
+        // threadIdx.x < 256 and lpr <= 32).
+        const int lpr = ((d.nx - x0 < TL::TW ? d.nx - x0 : TL::TW) + NPT - 1) / NPT;
+        if (lpr < TL::LPR) {
+            rb = (int)(((float)threadIdx.x + 0.5f) * (1.0f / (float)lpr));
+            cb = ((int)threadIdx.x - rb * lpr) * NPT;
+        }
+    }
     const int yb = y0 + rb < d.ny ? y0 + rb : d.ny - 1;
     R FxB[NPT], FyB[NPT];
 #pragma unroll
@@ -280,7 +291,7 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
     // slot i of all of them is one aligned vector of LDS.
     const int r = rb, c = cb;
     const int y = y0 + r;
-    if (y >= d.ny || x0 + c >= d.nx) return;
+    if ((PACK && r >= TL::TH) || y >= d.ny || x0 + c >= d.nx) return;
     R g[NPT][9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -406,7 +417,7 @@ __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, in
     const int x0 = tx * TL::TW, y0 = ty * TL::TH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
-        pair_tile<ST, FM, SCH, I, TL>(d, src, x0, y0, lds, tab);
+        pair_tile<ST, FM, SCH, I, TL, true>(d, src, x0, y0, lds, tab);
     } else {
         // The one-step node update in groups of 4 (TW / 4 threads per tile
         // row; with 2 nodes per thread in phase B only half the threads).
