@@ -144,3 +144,32 @@ def test_phase_b_stores_cover_each_row_and_its_padding_once(npt, tw):
                         written += range(x0 + c + 2, x0 + c + 4)
         want = list(range((nx + 3) // 4 * 4))
         assert sorted(written) == want, (npt, nx)
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+def test_packed_phase_b_covers_the_tile_once(tw, th):
+    # A batch tile at a lattice's right edge with `we` columns in the
+    # lattice maps thread t to row t // lpr and group t % lpr (lpr = the
+    # groups of npt nodes across `we`), the row from the float product
+    # (t + 1/2) * fl(1/lpr); every node of the tile inside the lattice is
+    # one thread's, once.
+    import numpy as np
+    npt = tw * th // 256
+    lpr_full = tw // npt
+    for we in range(1, tw + 1):
+        lpr = (we + npt - 1) // npt
+        t = np.arange(256)
+        if lpr < lpr_full:
+            rb = ((t.astype(np.float32) + np.float32(0.5)) * (np.float32(1.0) / np.float32(lpr))).astype(np.int64)
+            assert np.array_equal(rb, t // lpr), (tw, th, we)
+        else:
+            rb = t // lpr_full
+        cb = (t - rb * (lpr if lpr < lpr_full else lpr_full)) * npt
+        seen = {}
+        for r, c in zip(rb.tolist(), cb.tolist()):
+            if r >= th or c >= we:
+                continue
+            for k in range(npt):
+                seen[(r, c + k)] = seen.get((r, c + k), 0) + 1
+        want = {(r, x) for r in range(th) for x in range(we)}
+        assert want <= set(seen) and all(v == 1 for v in seen.values()), (tw, th, we)
