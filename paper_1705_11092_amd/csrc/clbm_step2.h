@@ -365,6 +365,287 @@ __device__ __forceinline__ void pair_tile(const LatDesc &d, int src, int x0, int
 }
 
 
+// Phase A's pull of the NPT consecutive nodes x0 .. x0 + NPT - 1 of row y
+// (Eq. 10): slot i of row y - e_y,i at x - e_x,i, or the node's own slot
+// opp(i) beyond a wall.  One element-aligned vector per slot, as the
+// one-step kernel loads them, with its patches of the x-periodic wraps (the
+// row's first node for e_x = +1, its last for e_x = -1; their sources are
+// loaded for every group, ahead of the vectors).  Lanes past nx read
+// padding and are not used.  Ordinary loads: the lines of the tile's edge
+// columns are the neighbouring tiles' halo.
+template <int ST, int NPT, typename I>
+__device__ __forceinline__ void pull_group(const LatDesc &d, const typename Storage<ST>::T *in, int y, int x0,
+                                           typename Storage<ST>::R (&g)[NPT][9], bool row_ends)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    constexpr I kU = sizeof(I) == 4 ? (I)sizeof(T) : (I)1;
+    I ro[9];
+    int dxs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Loc s = source_of(d, i, y);
+        ro[i] = ((I)s.dir * (I)d.dstride + row_at<I>(d, s.row)) * kU;
+        dxs[i] = s.dx;
+    }
+    if (!row_ends) {
+        // A tile that touches neither end of its rows: no wraps.
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const Pack<T, NPT> p = load_pack<T, NPT, false>(at<I>(in, ro[i] + (I)(x0 - dxs[i]) * kU));
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) g[k][i] = S::to_r(p.v[k]);
+        }
+        return;
+    }
+    const int kl = d.nx - 1 - x0;
+    const bool wrap_first = x0 == 0, wrap_last = kl >= 0 && kl < NPT;
+    T raw[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (ex_of(i) != 0) raw[i] = *at<I>(in, ro[i] + (I)(ex_of(i) == 1 ? d.nx - 1 : 0) * kU);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Pack<T, NPT> p = load_pack<T, NPT, false>(at<I>(in, ro[i] + (I)(x0 - dxs[i]) * kU));
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) g[k][i] = S::to_r(p.v[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (ex_of(i) == 1 && wrap_first && dxs[i] == 1) g[0][i] = S::to_r(raw[i]);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            if (ex_of(i) == -1 && wrap_last && k == kl && dxs[i] == -1) g[k][i] = S::to_r(raw[i]);
+    }
+}
+
+// A region node's post-collision values rv (storage type) into the LDS
+// entries of the tile nodes that pull them: slot i (1..8) of tile node
+// (a, b) goes to (a + e_y,i, b + e_x,i) when that node is in the tile; a
+// node in a wall row also fills its own entries for the slots that would
+// come from beyond the wall with its reversed values.  Slot 0 stays with
+// the node (phase B's thread is the node's own).
+template <typename T, typename TL>
+__device__ __forceinline__ void to_lds(const LatDesc &d, const T (&rv)[9], int a, int b, int y,
+                                       T (&lds)[8][TL::TH][TL::TW])
+{
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int ai = a + ey_of(i), bi = b + ex_of(i);
+        if (ai >= 0 && ai < TL::TH && bi >= 0 && bi < TL::TW) lds[i - 1][ai][bi] = rv[i];
+    }
+    if (d.bc_y) {
+        const bool lo = y == 0, hi = y == d.ny - 1;
+        if ((lo || hi) && a >= 0 && a < TL::TH && b >= 0 && b < TL::TW) {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                if ((ey_of(i) == 1 && lo) || (ey_of(i) == -1 && hi)) lds[i - 1][a][b] = rv[opp_of(i)];
+            }
+        }
+    }
+}
+
+// Node values in the storage type exactly as the one-step kernel stores
+// them: rounded to nearest, or stochastically with the operand of the
+// node's hash (its index and its post-collision slot 0).
+template <int ST>
+__device__ __forceinline__ void to_storage(const typename Storage<ST>::R (&g)[9], uint32_t node,
+                                           typename Storage<ST>::T (&rv)[9])
+{
+    using S = Storage<ST>;
+    if constexpr (S::kDither) {
+        const uint32_t h = hash32(__float_as_uint(g[0]) ^ (node * 0x9e3779b9u));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rv[i] = S::from_r_sr(g[i], sr_operand(h, i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) round_pair<ST>(g[i], g[i + 1], &rv[i]);
+        rv[8] = S::from_r(g[8]);
+    }
+}
+
+// The same two fused steps with thread t owning NPT consecutive nodes of
+// one tile row in both: phase A collides them (pulled as the one-step
+// kernel pulls them, slot 0 kept in registers) and then one node of the
+// region's ring, so LDS holds 8 slots and no tables.  It issues fewer
+// instructions per node update, which pays where VALU issue binds, the
+// 16-bit storage types (FP16 4096^2 191 -> 203 GLUPS, FP16-SR 170 -> 187,
+// their 256-lattice batches +17 %), and loses where it does not (FP32
+// 155 -> 152, FP64 84 -> 81, the FP32 batch 131 -> 126).  A tile at a
+// lattice's right edge (PACK) packs the threads onto the columns that lie
+// in the lattice, so that whole waves idle instead of every wave in part.
+template <int ST, int FM, int SCH, typename I, typename TL, bool PACK = false>
+__device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0, int y0,
+                                              typename Storage<ST>::T (&lds)[8][TL::TH][TL::TW])
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    using R = typename S::R;
+    constexpr int TW = TL::TW, TH = TL::TH, NPT = TL::NPT;
+    constexpr I kU = sizeof(I) == 4 ? (I)sizeof(T) : (I)1;  // address units per element
+    const T *in = static_cast<const T *>(d.buf[src]);
+    T *out = static_cast<T *>(d.buf[src ^ 1]);
+    const Rates<R> rt = rates_of<R>(d);
+    const int we = d.nx - x0 < TW ? d.nx - x0 : TW;  // the tile's columns and rows in the lattice
+    const int he = d.ny - y0 < TH ? d.ny - y0 : TH;
+
+    // This thread's nodes (rb, cb .. cb + NPT - 1) of the tile.  (Packed:
+    // the row from a float product, exact for threadIdx.x < 256 and lpr <=
+    // 32.)
+    int rb = threadIdx.x / TL::LPR, cb = (threadIdx.x % TL::LPR) * NPT;
+    if constexpr (PACK) {
+        const int lpr = (we + NPT - 1) / NPT;
+        if (lpr < TL::LPR) {
+            rb = (int)(((float)threadIdx.x + 0.5f) * (1.0f / (float)lpr));
+            cb = ((int)threadIdx.x - rb * lpr) * NPT;
+        }
+    }
+    const bool own = rb < he && cb < we;
+    const int yb = y0 + (rb < he ? rb : he - 1), xb = x0 + (cb < we ? cb : 0);
+    R F[2][NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) force_at<R, FM>(d, xb + k < d.nx ? xb + k : d.nx - 1, yb, F[0][k], F[1][k]);
+
+    // Phase A, step n + 1, on the thread's own nodes and on the region's
+    // ring: the nodes around the tile's part in the lattice, (we + 2) x
+    // (he + 2) less we x he, one per thread (top and bottom region rows,
+    // then the left and right columns between them, all periodic: a lattice
+    // narrower or lower than the region repeats; rows beyond a wall are not
+    // collided, bounce-back reads the node itself).  Every load is issued
+    // before any collision.
+    const int rw = we + 2, rh = he + 2, nring = 2 * rw + 2 * he;
+    const bool ring_wave = (int)(threadIdx.x & ~63u) < nring;
+    R g[NPT][9];
+    if (own) pull_group<ST, NPT, I>(d, in, yb, xb, g, x0 == 0 || x0 + TW >= d.nx);
+    R gr[9], Fxr = R(0), Fyr = R(0);
+    int rr = 0, cc = 0, yr = 0, xr = 0;
+    bool ring_keep = false;
+    if (ring_wave) {
+        const int k = (int)threadIdx.x < nring ? (int)threadIdx.x : nring - 1;
+        if (k < 2 * rw) {
+            rr = k < rw ? 0 : rh - 1;
+            cc = k < rw ? k : k - rw;
+        } else {
+            const int j = k - 2 * rw;
+            rr = 1 + (j < he ? j : j - he);
+            cc = j < he ? 0 : rw - 1;
+        }
+        yr = y0 - 1 + rr;
+        const bool beyond = d.bc_y && (yr < 0 || yr >= d.ny);
+        yr = beyond ? (yr < 0 ? 0 : d.ny - 1) : wrap_mod(yr, d.ny);
+        xr = wrap_mod(x0 - 1 + cc, d.nx);
+        ring_keep = (int)threadIdx.x < nring && !beyond;
+        force_at<R, FM>(d, xr, yr, Fxr, Fyr);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const Loc s = source_of(d, i, yr);
+            const int xs = s.dx == 0 ? xr : wrap_x(xr - s.dx, d.nx);
+            const I e = ((I)s.dir * (I)d.dstride + row_at<I>(d, s.row) + (I)xs) * kU;
+            gr[i] = S::to_r(*at<I>(in, e));
+        }
+    }
+    // The own nodes: slot 0 of each stays in registers for phase B, the
+    // other slots go to LDS.
+    T keep0[NPT];
+    if (own) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            collide<R, SCH>(g[k], F[0][k], F[1][k], rt);
+            T rv[9];
+            to_storage<ST>(g[k], (uint32_t)yb * (uint32_t)d.nx + (uint32_t)(xb + k), rv);
+            keep0[k] = rv[0];
+            if (cb + k < we) to_lds<T, TL>(d, rv, rb, cb + k, yb, lds);
+        }
+    }
+    if (ring_wave) {
+        collide<R, SCH>(gr, Fxr, Fyr, rt);
+        if (ring_keep) {
+            T rv[9];
+            to_storage<ST>(gr, (uint32_t)yr * (uint32_t)d.nx + (uint32_t)xr, rv);
+            to_lds<T, TL>(d, rv, rr - 1, cc - 1, yr, lds);
+        }
+    }
+    __syncthreads();
+
+    // Phase B, step n + 2 on the thread's nodes: slot 0 from registers, the
+    // others as one aligned vector of LDS each.
+    if (!own) return;
+    const int r = rb, c = cb;
+    const int y = y0 + r;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) g[k][0] = S::to_r(keep0[k]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const typename VecTypes<T, NPT>::tight v = *reinterpret_cast<const typename VecTypes<T, NPT>::tight *>(&lds[i - 1][r][c]);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) g[k][i] = S::to_r(v[k]);
+    }
+    Pack<T, NPT> q[9];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) collide<R, SCH>(g[k], F[0][k], F[1][k], rt);
+    if constexpr (S::kDither) {
+        // The one-step kernel's stochastic rounding of the nodes, in pairs.
+        uint32_t h[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const uint32_t node = (uint32_t)y * (uint32_t)d.nx + (uint32_t)(x0 + c + k);
+            h[k] = hash32(__float_as_uint(g[k][0]) ^ (node * 0x9e3779b9u));
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+#pragma unroll
+            for (int k = 0; k < NPT; k += 2) {
+                const auto two = S::from_r_sr2(g[k][i], sr_operand(h[k], i), g[k + 1][i], sr_operand(h[k + 1], i));
+                q[i].v[k] = two[0];
+                q[i].v[k + 1] = two[1];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; k += 2)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) round_pair<ST>(g[k][i], g[k + 1][i], &q[i].v[k]);
+    }
+    const I ob = row_at<I>(d, y) + (I)(x0 + c);
+    if (x0 + c + NPT <= d.nx) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) store_pack<T, NPT, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+        // NPT = 2: a row whose length leaves 1 or 2 in its last group of 4
+        // has that group's padding half written below.
+        if constexpr (NPT == 2) {
+            if (x0 + c + 2 == d.nx && (d.nx & 3)) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Pack<T, 2> pad;
+                    pad.v[0] = pad.v[1] = q[i].v[1];
+                    store_pack<T, 2, true>(elem<I>(out, ob + (I)2 + (I)i * (I)d.dstride), pad);
+                }
+            }
+        }
+    } else {
+        // The row's last group: real nodes, then copies of the last one in
+        // the padding up to the next multiple of 4, so the row's cache
+        // lines are written whole as the one-step kernel writes them.
+        const int kl = d.nx - 1 - x0 - c;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+#pragma unroll
+            for (int k = 1; k < NPT; ++k)
+                if (k > kl) q[i].v[k] = q[i].v[k - 1];
+            store_pack<T, NPT, true>(elem<I>(out, ob + (I)i * (I)d.dstride), q[i]);
+            if constexpr (NPT == 2) {
+                // The last group of 4 ends 2 further on.
+                if ((x0 + c) % 4 == 0) {
+                    Pack<T, 2> pad;
+                    pad.v[0] = pad.v[1] = q[i].v[1];
+                    store_pack<T, 2, true>(elem<I>(out, ob + (I)2 + (I)i * (I)d.dstride), pad);
+                }
+            }
+        }
+    }
+}
+
+
 // Tile t of a lattice of tiles_x x tiles_y tiles, walked in vertical strips
 // of sw tile columns (the last strip narrower): within a strip row by row,
 // so the tile above was taken sw tiles earlier and its lines are still in
@@ -383,11 +664,33 @@ __device__ __forceinline__ void strip_tile(int t, int tiles_x, int tiles_y, int 
     }
 }
 
+// The LDS of a pair tile: 9 slots and the coordinate tables (pair_tile),
+// or, for 16-bit storage, 8 slots (pair_tile_own).
+template <int ST>
+constexpr bool kOwnNodes = ST == ST_F16 || ST == ST_BF16 || ST == ST_F16_SR || ST == ST_BF16_SR;
+template <int ST, typename I, typename TL, bool OWN = kOwnNodes<ST>>
+struct PairLds {
+    alignas(16) typename Storage<ST>::T v[9][TL::TH][TL::TW];
+    TileTabs<I, TL> tab;
+};
+template <int ST, typename I, typename TL>
+struct PairLds<ST, I, TL, true> {
+    alignas(16) typename Storage<ST>::T v[8][TL::TH][TL::TW];
+};
+
+template <int ST, int FM, int SCH, typename I, typename TL, bool PACK>
+__device__ __forceinline__ void pair_step(const LatDesc &d, int src, int x0, int y0, PairLds<ST, I, TL> &m)
+{
+    if constexpr (kOwnNodes<ST>)
+        pair_tile_own<ST, FM, SCH, I, TL, PACK>(d, src, x0, y0, m.v);
+    else
+        pair_tile<ST, FM, SCH, I, TL, PACK>(d, src, x0, y0, m.v, m.tab);
+}
+
 template <int ST, int FM, int SCH, typename I, typename TL>
 __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
 {
-    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
-    __shared__ TileTabs<I, TL> tab;
+    __shared__ PairLds<ST, I, TL> lds;
     // xcd_order gives each XCD a contiguous range of tile numbers, and the
     // strip walk puts a tile's left neighbour one tile and the one above it
     // sw tiles earlier in that range, so the halo lines a tile shares with
@@ -396,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
     const int t = (int)xcd_order(blockIdx.x, gridDim.x);
     int tx, ty;
     strip_tile(t, tiles_x, tiles_y, sw, tx, ty);
-    pair_tile<ST, FM, SCH, I, TL>(d, src, tx * TL::TW, ty * TL::TH, lds, tab);
+    pair_step<ST, FM, SCH, I, TL, false>(d, src, tx * TL::TW, ty * TL::TH, lds);
 }
 
 // Tile lt of lattice d in batch pair substep `pair`: a lattice with at least
@@ -405,9 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
 // be odd).  The buffer parity of these lattices counts launches: pair p
 // reads buffer parity + p.  Within a lattice the tiles take the strip walk.
 template <int ST, int FM, int SCH, typename I, typename TL>
-__device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair,
-                                                typename Storage<ST>::T (&lds)[9][TL::TH][TL::TW],
-                                                TileTabs<I, TL> &tab)
+__device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair, PairLds<ST, I, TL> &lds)
 {
     const int left = d.steps - 2 * pair;
     const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
@@ -417,7 +718,7 @@ __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, in
     const int x0 = tx * TL::TW, y0 = ty * TL::TH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
-        pair_tile<ST, FM, SCH, I, TL, true>(d, src, x0, y0, lds, tab);
+        pair_step<ST, FM, SCH, I, TL, true>(d, src, x0, y0, lds);
     } else {
         // The one-step node update in groups of 4 (TW / 4 threads per tile
         // row; with 2 nodes per thread in phase B only half the threads).
@@ -435,12 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ l
                                                    const int32_t *__restrict__ tile_lat, int64_t ntiles,
                                                    int pair)
 {
-    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
-    __shared__ TileTabs<I, TL> tab;
+    __shared__ PairLds<ST, I, TL> lds;
     const int64_t t = xcd_order(blockIdx.x, ntiles);
     const LatDesc &d = lats[tile_lat[t]];
     if (d.steps - 2 * pair <= 0) return;  // the whole block: one lattice per tile
-    batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds, tab);
+    batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds);
 }
 
 // The same with a persistent grid: block b walks one contiguous range of
@@ -452,8 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ 
                                                     const int32_t *__restrict__ tile_lat, int64_t ntiles,
                                                     int pair)
 {
-    __shared__ __align__(16) typename Storage<ST>::T lds[9][TL::TH][TL::TW];
-    __shared__ TileTabs<I, TL> tab;
+    __shared__ PairLds<ST, I, TL> lds;
     const int64_t G = gridDim.x;
     const int64_t b = xcd_order(blockIdx.x, G);
     const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
@@ -461,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ 
     for (int64_t t = lo; t < hi; ++t) {
         const int jn = t + 1 < hi ? tile_lat[t + 1] : j;
         const LatDesc &d = lats[j];
-        if (d.steps - 2 * pair > 0) batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds, tab);
+        if (d.steps - 2 * pair > 0) batch_pair_tile<ST, FM, SCH, I, TL>(d, t - d.tile0, pair, lds);
         j = jn;
         // The next tile's tables and phase A overwrite what this tile's
         // phase B still reads.

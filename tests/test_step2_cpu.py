@@ -173,3 +173,87 @@ def test_packed_phase_b_covers_the_tile_once(tw, th):
                 seen[(r, c + k)] = seen.get((r, c + k), 0) + 1
         want = {(r, x) for r in range(th) for x in range(we)}
         assert want <= set(seen) and all(v == 1 for v in seen.values()), (tw, th, we)
+
+
+def _own_node_writes(nx, ny, bc, x0, y0, tw, th, npt, pack):
+    """The 16-bit storage types' pair step: thread t owns its phase-B nodes
+    in phase A too (slot 0 stays in its registers), and the region's ring
+    (the nodes around the tile's part in the lattice) is collided one node
+    per thread.  Map (slot 1..8, tile row, tile column) -> source, as those
+    writes fill it, checking each entry is written once and in bounds, and
+    that every tile node in the lattice is one thread's."""
+    import numpy as np
+    we, he = min(tw, nx - x0), min(th, ny - y0)
+    lpr_full = tw // npt
+    writes, owners = {}, {}
+
+    def put(key, val):
+        assert 1 <= key[0] <= 8 and 0 <= key[1] < th and 0 <= key[2] < tw
+        assert key not in writes, ("written twice", key)
+        writes[key] = val
+
+    def to_lds(a, b, x, y):
+        for i in range(1, 9):
+            ai, bi = a + EY[i], b + EX[i]
+            if 0 <= ai < th and 0 <= bi < tw:
+                put((i, ai, bi), (x, y, i))
+        if bc:
+            lo, hi = y == 0, y == ny - 1
+            if (lo or hi) and 0 <= a < th and 0 <= b < tw:
+                for i in range(1, 9):
+                    if (EY[i] == 1 and lo) or (EY[i] == -1 and hi):
+                        put((i, a, b), (x, y, OPP[i]))
+
+    for t in range(256):
+        rb, cb = t // lpr_full, (t % lpr_full) * npt
+        if pack:
+            lpr = (we + npt - 1) // npt
+            if lpr < lpr_full:
+                rb = int((np.float32(t) + np.float32(0.5)) * (np.float32(1.0) / np.float32(lpr)))
+                cb = (t - rb * lpr) * npt
+        if not (rb < he and cb < we):
+            continue
+        for k in range(npt):
+            if cb + k < we:
+                assert (rb, cb + k) not in owners
+                owners[(rb, cb + k)] = t
+                to_lds(rb, cb + k, x0 + cb + k, y0 + rb)
+    rw, rh = we + 2, he + 2
+    nring = 2 * rw + 2 * he
+    assert nring <= 256
+    for k in range(nring):
+        if k < 2 * rw:
+            rr, cc = (0, k) if k < rw else (rh - 1, k - rw)
+        else:
+            j = k - 2 * rw
+            rr, cc = (1 + j, 0) if j < he else (1 + j - he, rw - 1)
+        y = y0 - 1 + rr
+        if bc and (y < 0 or y >= ny):
+            continue
+        to_lds(rr - 1, cc - 1, (x0 - 1 + cc) % nx, y % ny)
+    assert set(owners) == {(r, c) for r in range(he) for c in range(we)}
+    return writes
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+@pytest.mark.parametrize("pack", [False, True])
+@pytest.mark.parametrize("nx,ny,bc", [(300, 70, 1), (300, 70, 0), (65, 17, 1), (33, 1, 1), (70, 2, 1),
+                                      (2, 2, 0), (19, 1, 0), (1, 17, 1), (129, 33, 1), (200, 40, 0),
+                                      (40, 100, 0), (31, 33, 1), (1, 1, 0), (1, 1, 1), (4, 3, 1)])
+def test_own_node_pair_step_fills_the_pulled_values(nx, ny, bc, tw, th, pack):
+    npt = tw * th // 256
+    tiles_x, tiles_y = (nx + tw - 1) // tw, (ny + th - 1) // th
+    for ty in range(tiles_y):
+        for tx in range(tiles_x):
+            x0, y0 = tx * tw, ty * th
+            writes = _own_node_writes(nx, ny, bc, x0, y0, tw, th, npt, pack)
+            for r in range(min(th, ny - y0)):
+                for c in range(min(tw, nx - x0)):
+                    x, y = x0 + c, y0 + r
+                    for i in range(1, 9):
+                        ys = y - EY[i]
+                        if bc and (ys < 0 or ys >= ny):
+                            want = (x, y, OPP[i])
+                        else:
+                            want = ((x - EX[i]) % nx, ys % ny, i)
+                        assert writes.get((i, r, c)) == want, (nx, ny, bc, tx, ty, r, c, i)
