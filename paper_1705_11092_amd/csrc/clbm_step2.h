@@ -469,9 +469,9 @@ __device__ __forceinline__ void to_storage(const typename Storage<ST>::R (&g)[9]
 // kernel pulls them, slot 0 kept in registers) and then one node of the
 // region's ring, so LDS holds 8 slots and no tables.  It issues fewer
 // instructions per node update, which pays where VALU issue binds, the
-// 16-bit storage types (FP16 4096^2 191 -> 203 GLUPS, FP16-SR 170 -> 187,
-// their 256-lattice batches +17 %), and loses where it does not (FP32
-// 155 -> 152, FP64 84 -> 81, the FP32 batch 131 -> 126).  A tile at a
+// 16-bit storage types (FP16 4096^2 191 -> 203 GLUPS, FP16-SR 170 -> 183,
+// BF16-SR 170 -> 187, their 256-lattice batches +17 %), and loses where it
+// does not (FP32 155 -> 152, FP64 84 -> 81, the FP32 batch 131 -> 126).  A tile at a
 // lattice's right edge (PACK) packs the threads onto the columns that lie
 // in the lattice, so that whole waves idle instead of every wave in part.
 template <int ST, int FM, int SCH, typename I, typename TL, bool PACK = false>
