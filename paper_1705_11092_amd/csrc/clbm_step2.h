@@ -536,12 +536,26 @@ __device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0,
         xr = wrap_mod(x0 - 1 + cc, d.nx);
         ring_keep = (int)threadIdx.x < nring && !beyond;
         force_at<R, FM>(d, xr, yr, Fxr, Fyr);
+        // The pull sources (Eq. 10) from three row and three column offsets:
+        // rows y - 1 and y + 1 (periodic, or the node's own row with its
+        // reversed slot beyond a wall), columns x - 1, x, x + 1 (periodic).
+        const bool in_m = !d.bc_y || yr >= 1, in_p = !d.bc_y || yr + 1 < d.ny;
+        const I r0 = row_at<I>(d, yr);
+        const I rm = in_m ? row_at<I>(d, yr == 0 ? d.ny - 1 : yr - 1) : r0;
+        const I rq = in_p ? row_at<I>(d, yr == d.ny - 1 ? 0 : yr + 1) : r0;
+        const I cm = (I)(xr == 0 ? d.nx - 1 : xr - 1), c0 = (I)xr, cp = (I)(xr == d.nx - 1 ? 0 : xr + 1);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const Loc s = source_of(d, i, yr);
-            const int xs = s.dx == 0 ? xr : wrap_x(xr - s.dx, d.nx);
-            const I e = ((I)s.dir * (I)d.dstride + row_at<I>(d, s.row) + (I)xs) * kU;
-            gr[i] = S::to_r(*at<I>(in, e));
+            const I xs = ex_of(i) == 1 ? cm : (ex_of(i) == -1 ? cp : c0);
+            const I so = (I)i * (I)d.dstride, sb = (I)opp_of(i) * (I)d.dstride;
+            I e;
+            if (ey_of(i) == 0)
+                e = r0 + so + xs;
+            else if (ey_of(i) == 1)
+                e = in_m ? rm + so + xs : r0 + sb + c0;
+            else
+                e = in_p ? rq + so + xs : r0 + sb + c0;
+            gr[i] = S::to_r(*at<I>(in, e * kU));
         }
     }
     // The own nodes: slot 0 of each stays in registers for phase B, the
