@@ -380,13 +380,23 @@ __device__ __forceinline__ void pull_group(const LatDesc &d, const typename Stor
     using S = Storage<ST>;
     using T = typename S::T;
     constexpr I kU = sizeof(I) == 4 ? (I)sizeof(T) : (I)1;
+    // The pull sources of row y (Eq. 10): rows y - 1, y, y + 1 (periodic),
+    // or, where one lies beyond a wall, the node's own reversed slot.  The
+    // three row offsets are formed once and each slot picks one, instead of
+    // a multiply per slot.
+    const bool in_m = !d.bc_y || y >= 1, in_p = !d.bc_y || y + 1 < d.ny;
+    const I r0 = row_at<I>(d, y);
+    const I rm = in_m ? row_at<I>(d, y == 0 ? d.ny - 1 : y - 1) : r0;
+    const I rq = in_p ? row_at<I>(d, y == d.ny - 1 ? 0 : y + 1) : r0;
     I ro[9];
     int dxs[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const Loc s = source_of(d, i, y);
-        ro[i] = ((I)s.dir * (I)d.dstride + row_at<I>(d, s.row)) * kU;
-        dxs[i] = s.dx;
+        const I so = (I)i * (I)d.dstride, sb = (I)opp_of(i) * (I)d.dstride;
+        const bool pulled = ey_of(i) == 0 || (ey_of(i) == 1 ? in_m : in_p);
+        const I row = ey_of(i) == 0 ? r0 : (ey_of(i) == 1 ? rm : rq);
+        ro[i] = (pulled ? row + so : r0 + sb) * kU;
+        dxs[i] = pulled ? ex_of(i) : 0;
     }
     if (!row_ends) {
         // A tile that touches neither end of its rows: no wraps.
