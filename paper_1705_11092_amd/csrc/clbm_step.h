@@ -74,11 +74,28 @@ __device__ __forceinline__ void step_group(const LatDesc &d, int src, int y, int
 
     const T *rowp[9];
     int dxs[9];
+    if constexpr (AA) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const Loc s = AA ? aa_source(d, i, y, src) : source_of(d, i, y);
-        rowp[i] = in + (int64_t)s.dir * d.dstride + row_base(d, s.row);
-        dxs[i] = s.dx;
+        for (int i = 0; i < 9; ++i) {
+            const Loc s = aa_source(d, i, y, src);
+            rowp[i] = in + (int64_t)s.dir * d.dstride + row_base(d, s.row);
+            dxs[i] = s.dx;
+        }
+    } else {
+        // Two buffers: the rows above, at and below y (periodic), or beyond
+        // a wall the node's own reversed slot (Eq. 10); the three row
+        // offsets are formed once and each slot picks one.
+        const bool in_m = !d.bc_y || y >= 1, in_p = !d.bc_y || y + 1 < d.ny;
+        const int64_t r0 = row_base(d, y);
+        const int64_t rm = in_m ? row_base(d, y == 0 ? d.ny - 1 : y - 1) : r0;
+        const int64_t rq = in_p ? row_base(d, y == d.ny - 1 ? 0 : y + 1) : r0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool pulled = ey_of(i) == 0 || (ey_of(i) == 1 ? in_m : in_p);
+            const int64_t row = ey_of(i) == 0 ? r0 : (ey_of(i) == 1 ? rm : rq);
+            rowp[i] = pulled ? in + (int64_t)i * d.dstride + row : in + (int64_t)opp_of(i) * d.dstride + r0;
+            dxs[i] = pulled ? ex_of(i) : 0;
+        }
     }
 
     // The force first: for the table-driven modes its loads then issue
