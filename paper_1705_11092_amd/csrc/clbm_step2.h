@@ -439,17 +439,22 @@ template <typename T, typename TL>
 __device__ __forceinline__ void to_lds(const LatDesc &d, const T (&rv)[9], int a, int b, int y,
                                        T (&lds)[8][TL::TH][TL::TW])
 {
+    // One address for the node, each slot's entry a constant offset from it
+    // (for a ring node left of or above the tile it lies in the guard ahead
+    // of the slots; only entries inside the tile are written).
+    constexpr int kPlane = TL::TH * TL::TW;
+    T *const lp = &lds[0][0][0] + (a * TL::TW + b);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const int ai = a + ey_of(i), bi = b + ex_of(i);
-        if (ai >= 0 && ai < TL::TH && bi >= 0 && bi < TL::TW) lds[i - 1][ai][bi] = rv[i];
+        if (ai >= 0 && ai < TL::TH && bi >= 0 && bi < TL::TW) lp[(i - 1) * kPlane + ey_of(i) * TL::TW + ex_of(i)] = rv[i];
     }
     if (d.bc_y) {
         const bool lo = y == 0, hi = y == d.ny - 1;
         if ((lo || hi) && a >= 0 && a < TL::TH && b >= 0 && b < TL::TW) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                if ((ey_of(i) == 1 && lo) || (ey_of(i) == -1 && hi)) lds[i - 1][a][b] = rv[opp_of(i)];
+                if ((ey_of(i) == 1 && lo) || (ey_of(i) == -1 && hi)) lp[(i - 1) * kPlane] = rv[opp_of(i)];
             }
         }
     }
@@ -699,6 +704,10 @@ struct PairLds {
 };
 template <int ST, typename I, typename TL>
 struct PairLds<ST, I, TL, true> {
+    // A guard of TW + 8 elements ahead of the slots: the node address that
+    // to_lds forms for a ring node at region row or column 0 lies up to
+    // TW + 1 elements before slot 1's first entry.
+    typename Storage<ST>::T guard[TL::TW + 8];
     alignas(16) typename Storage<ST>::T v[8][TL::TH][TL::TW];
 };
 
