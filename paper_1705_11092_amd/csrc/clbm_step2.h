@@ -547,8 +547,10 @@ __device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0,
         }
         yr = y0 - 1 + rr;
         const bool beyond = d.bc_y && (yr < 0 || yr >= d.ny);
-        yr = beyond ? (yr < 0 ? 0 : d.ny - 1) : wrap_mod(yr, d.ny);
-        xr = wrap_mod(x0 - 1 + cc, d.nx);
+        // yr lies in [y0 - 1, y0 + he] and x0 - 1 + cc in [x0 - 1, x0 + we],
+        // so within [-1, n] and a single wrap brings them into the lattice.
+        yr = beyond ? (yr < 0 ? 0 : d.ny - 1) : wrap_x(yr, d.ny);
+        xr = wrap_x(x0 - 1 + cc, d.nx);
         ring_keep = (int)threadIdx.x < nring && !beyond;
         force_at<R, FM>(d, xr, yr, Fxr, Fyr);
         // The pull sources (Eq. 10) from three row and three column offsets:
