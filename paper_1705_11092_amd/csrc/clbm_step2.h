@@ -695,6 +695,59 @@ __device__ __forceinline__ void strip_tile(int t, int tiles_x, int tiles_y, int 
     }
 }
 
+// Division of 0 <= n < 2^31 by a fixed d >= 1 as a multiply and a shift
+// (Granlund and Montgomery's round-up method): with 2^(s-1) < d <= 2^s,
+// m = ceil(2^(31+s) / d) is below 2^32 and m d - 2^(31+s) < d <= 2^s, so
+// n m / 2^(31+s) exceeds n / d by less than 1/d and its floor is floor(n / d).
+// With n and the divisor uniform, the kernel does it on the scalar unit.
+struct FastDiv {
+    uint32_t m;
+    int32_t sh;
+};
+inline FastDiv fast_div(uint32_t d)
+{
+    int s = 0;
+    while (s < 31 && (1u << s) < d) ++s;
+    const uint64_t p = (uint64_t)1 << (31 + s);
+    return FastDiv{(uint32_t)((p + d - 1) / d), 31 + s};
+}
+__device__ __forceinline__ int div_by(int n, FastDiv f)
+{
+    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
+}
+
+// The strip walk of one lattice's tiles with its divisions prepared on the
+// host (strip_tile's arithmetic without integer divides in the kernel).
+struct StripWalk {
+    int32_t sw, tiles_y, full, in_full, w;  // strip width, tile rows, full strips, their tiles, last strip's width
+    FastDiv by_strip, by_sw, by_w;          // by sw * tiles_y, sw and w
+};
+inline StripWalk strip_walk(int tiles_x, int tiles_y, int sw)
+{
+    StripWalk p;
+    p.sw = sw;
+    p.tiles_y = tiles_y;
+    p.full = tiles_x / sw;
+    p.in_full = p.full * sw * tiles_y;
+    p.w = tiles_x - p.full * sw;
+    p.by_strip = fast_div((uint32_t)(sw * tiles_y));
+    p.by_sw = fast_div((uint32_t)sw);
+    p.by_w = fast_div((uint32_t)(p.w > 0 ? p.w : 1));
+    return p;
+}
+__device__ __forceinline__ void strip_tile(int t, const StripWalk &p, int &tx, int &ty)
+{
+    if (t < p.in_full) {
+        const int st = div_by(t, p.by_strip), i = t - st * (p.sw * p.tiles_y);
+        ty = div_by(i, p.by_sw);
+        tx = st * p.sw + (i - ty * p.sw);
+    } else {
+        const int i = t - p.in_full;
+        ty = div_by(i, p.by_w);
+        tx = p.full * p.sw + (i - ty * p.w);
+    }
+}
+
 // The LDS of a pair tile: 9 slots and the coordinate tables (pair_tile),
 // or, for 16-bit storage, 8 slots (pair_tile_own).
 template <int ST>
@@ -723,17 +776,16 @@ __device__ __forceinline__ void pair_step(const LatDesc &d, int src, int x0, int
 }
 
 template <int ST, int FM, int SCH, typename I, typename TL>
-__global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, int sw)
+__global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, StripWalk sw)
 {
     __shared__ PairLds<ST, I, TL> lds;
     // xcd_order gives each XCD a contiguous range of tile numbers, and the
     // strip walk puts a tile's left neighbour one tile and the one above it
     // sw tiles earlier in that range, so the halo lines a tile shares with
     // them are still in that XCD's L2.
-    const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
     const int t = (int)xcd_order(blockIdx.x, gridDim.x);
     int tx, ty;
-    strip_tile(t, tiles_x, tiles_y, sw, tx, ty);
+    strip_tile(t, sw, tx, ty);
     pair_step<ST, FM, SCH, I, TL, false>(d, src, tx * TL::TW, ty * TL::TH, lds);
 }
 
@@ -824,7 +876,7 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
     const bool small = elems * (int64_t)sizeof(typename Storage<ST>::T) + 4096 < ((int64_t)1 << 32);
     const int tiles_x = (d.nx + TL::TW - 1) / TL::TW;
     constexpr int kSw = kStripNodes / TL::TW;
-    const int sw = tiles_x < kSw ? tiles_x : kSw;
+    const StripWalk sw = strip_walk(tiles_x, (d.ny + TL::TH - 1) / TL::TH, tiles_x < kSw ? tiles_x : kSw);
     switch (d.force_mode * 2 + d.scheme) {
 #define CLBM_S2(FM, SCH)                                                              \
     case FM * 2 + SCH:                                                                \

@@ -11,9 +11,13 @@ reversed slot into the entry its absent neighbour would fill.  These tests
 restate that arithmetic and check that the walk visits every tile once,
 that every LDS entry phase B reads is written exactly once, by the source
 the pull with half-way bounce-back names, that the region row of a region
-node comes out exact from its float product, and that phase B's stores
-cover each row and its padding up to the next multiple of 4 exactly once.
+node comes out exact from its float product, that the multiply-and-shift
+divisions of the single-lattice walk equal integer division, and that
+phase B's stores cover each row and its padding up to the next multiple of
+4 exactly once.
 """
+import random
+
 import pytest
 
 EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
@@ -47,6 +51,61 @@ def test_strip_walk_visits_every_tile_once(nx, ny, tw, th):
     # Within a full strip the tile above is sw tiles earlier.
     if tiles_y > 1 and tiles_x >= sw:
         assert seen[sw] == (seen[0][0], seen[0][1] + 1)
+
+
+def fast_div(d):
+    """The kernel's divisor d >= 1 as (m, sh): m = ceil(2^(31+s) / d) with
+    2^(s-1) < d <= 2^s, sh = 31 + s."""
+    s = 0
+    while s < 31 and (1 << s) < d:
+        s += 1
+    return -(-(1 << (31 + s)) // d), 31 + s
+
+
+def div_by(n, f):
+    m, sh = f
+    assert 0 <= m < 1 << 32 and 0 <= n < 1 << 31
+    return ((n * m) & ((1 << 64) - 1)) >> sh
+
+
+def test_fast_division_is_exact_below_2_31():
+    rng = random.Random(7)
+    divisors = list(range(1, 3000)) + [(1 << k) + o for k in range(12, 31) for o in (-1, 0, 1)]
+    divisors += [rng.randrange(1, 1 << 31) for _ in range(300)] + [(1 << 31) - 1]
+    for d in divisors:
+        f = fast_div(d)
+        ns = {0, 1, d - 1, d, d + 1, 2 * d - 1, (1 << 31) - 1, (1 << 31) - 1 - d}
+        ns |= {rng.randrange(0, 1 << 31) for _ in range(20)}
+        ns |= {q * d + r for q in (1, 7, (1 << 31) // d - 1) for r in (0, d - 1)}
+        for n in ns:
+            if 0 <= n < 1 << 31:
+                assert div_by(n, f) == n // d, (d, n)
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+@pytest.mark.parametrize("nx,ny", [(1, 1), (65, 17), (300, 70), (1030, 9), (4096, 4096), (520, 200),
+                                   (32768, 32768)])
+def test_strip_walk_with_prepared_divisions(nx, ny, tw, th):
+    """The single-lattice walk (divisions by sw * tiles_y, sw and the last
+    strip's width prepared on the host) names the same tile as strip_tile."""
+    tiles_x, tiles_y = (nx + tw - 1) // tw, (ny + th - 1) // th
+    sw = min(tiles_x, STRIP_NODES // tw)
+    full = tiles_x // sw
+    in_full, w = full * sw * tiles_y, tiles_x - full * sw
+    by_strip, by_sw, by_w = fast_div(sw * tiles_y), fast_div(sw), fast_div(w if w > 0 else 1)
+    n = tiles_x * tiles_y
+    ts = range(n) if n <= 20000 else sorted(t for t in {0, n - 1, in_full - 1, in_full} | set(range(0, n, 997)) if 0 <= t < n)
+    for t in ts:
+        if t < in_full:
+            st = div_by(t, by_strip)
+            i = t - st * (sw * tiles_y)
+            ty = div_by(i, by_sw)
+            got = (st * sw + (i - ty * sw), ty)
+        else:
+            i = t - in_full
+            ty = div_by(i, by_w)
+            got = (full * sw + (i - ty * w), ty)
+        assert got == strip_tile(t, tiles_x, tiles_y, sw), (t, nx, ny)
 
 
 def _phase_a_writes(nx, ny, bc, x0, y0, tw=TW, th=TH):
