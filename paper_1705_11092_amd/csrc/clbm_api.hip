@@ -846,9 +846,13 @@ void batch_geometry(clbm_batch *b)
         while (pos < b->order.size() && group_key(b, b->lats[b->order[pos]]) == key) {
             LatDesc d = b->lats[b->order[pos]]->d;
             clbm::tile_geometry(d.pitch, d.ny, vec, &d.tpr, &d.inv_tpr, &d.ntiles);
-            if (pairs)  // tiles of the two-step kernel in the group's shape
-                d.ntiles = (int64_t)((d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape)) *
-                           ((d.ny + clbm::tile_h(shape, st) - 1) / clbm::tile_h(shape, st));
+            if (pairs) {  // tiles of the two-step kernel in the group's shape, and their walk
+                const int tx = (d.nx + clbm::tile_w(shape) - 1) / clbm::tile_w(shape);
+                const int ty = (d.ny + clbm::tile_h(shape, st) - 1) / clbm::tile_h(shape, st);
+                const int sw = clbm::kStripNodes / clbm::tile_w(shape);
+                d.ntiles = (int64_t)tx * ty;
+                d.walk = clbm::strip_walk(tx, ty, tx < sw ? tx : sw);
+            }
             d.vec = vec;
             d.pairs = pairs ? 1 : 0;
             d.tile0 = tiles;
@@ -890,6 +894,7 @@ int batch_upload(clbm_batch *b, const int64_t *nsteps, void *spare = nullptr)
             d.vec = g.vec;
             d.tile0 = g.tile0;
             d.ntiles = g.ntiles;
+            d.walk = g.walk;
             d.pairs = g.pairs;
             d.parity = h->parity;
             d.steps = (int32_t)nsteps[b->order[pos]];

@@ -61,6 +61,48 @@ inline int64_t row_pitch(int nx, int eb)
 // rows by 3-6 %; a 4096^2 FP32 lattice (16 KB rows) keeps R = 1.
 constexpr int64_t kBlockRunBytes = 16384;
 
+// Nodes across a strip of the tile walk (8 tiles of 64 columns, 16 of 32).
+// Measured on FP64 4096^2 with 32 x 16 tiles: strips of 128, 256, 512 and
+// 1024 nodes gave 48, 56, 81 and 81 GLUPS.
+constexpr int kStripNodes = 512;
+
+// Division of 0 <= n < 2^31 by a fixed d >= 1 as a multiply and a shift
+// (Granlund and Montgomery's round-up method): with 2^(s-1) < d <= 2^s,
+// m = ceil(2^(31+s) / d) is below 2^32 and m d - 2^(31+s) < d <= 2^s, so
+// n m / 2^(31+s) exceeds n / d by less than 1/d and its floor is floor(n / d).
+// With n and the divisor uniform, the kernel does it on the scalar unit.
+struct FastDiv {
+    uint32_t m;
+    int32_t sh;
+};
+inline FastDiv fast_div(uint32_t d)
+{
+    int s = 0;
+    while (s < 31 && (1u << s) < d) ++s;
+    const uint64_t p = (uint64_t)1 << (31 + s);
+    return FastDiv{(uint32_t)((p + d - 1) / d), 31 + s};
+}
+
+// The strip walk of one lattice's tiles with its divisions prepared on the
+// host (strip_tile's arithmetic without integer divides in the kernel).
+struct StripWalk {
+    int32_t sw, tiles_y, full, in_full, w;  // strip width, tile rows, full strips, their tiles, last strip's width
+    FastDiv by_strip, by_sw, by_w;          // by sw * tiles_y, sw and w
+};
+inline StripWalk strip_walk(int tiles_x, int tiles_y, int sw)
+{
+    StripWalk p;
+    p.sw = sw;
+    p.tiles_y = tiles_y;
+    p.full = tiles_x / sw;
+    p.in_full = p.full * sw * tiles_y;
+    p.w = tiles_x - p.full * sw;
+    p.by_strip = fast_div((uint32_t)(sw * tiles_y));
+    p.by_sw = fast_div((uint32_t)sw);
+    p.by_w = fast_div((uint32_t)(p.w > 0 ? p.w : 1));
+    return p;
+}
+
 // Everything a kernel needs to step one lattice.  Passed by value to the
 // single-lattice kernel and stored in a device array for batches.
 struct LatDesc {
@@ -84,6 +126,7 @@ struct LatDesc {
     int32_t pairs;       // batch: steps go two per launch (64 x 16 tiles, parity counts launches)
     int64_t tile0;       // batch: first tile of this lattice in its group
     int64_t ntiles;      // batch: tiles of this lattice
+    StripWalk walk;      // batch, two steps per launch: the strip walk of its tiles in the group's shape
     double inv_tpr;      // 1 / tpr, for the tile decode
     double Fx, Fy;       // FM_CONST force density
     double sc_g, sc_psi0, sc_rho;  // FM_SC: G, psi0 and rho_ref of psi = psi0 exp(-rho_ref/rho)

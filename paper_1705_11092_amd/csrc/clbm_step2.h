@@ -44,10 +44,6 @@ using T32x32 = Tile<32, 32>;
 using T64x8 = Tile<64, 8, 2>;
 using T32x16 = Tile<32, 16, 2>;
 
-// Nodes across a strip of the tile walk (8 tiles of 64 columns, 16 of 32).
-// Measured on FP64 4096^2 with 32 x 16 tiles: strips of 128, 256, 512 and
-// 1024 nodes gave 48, 56, 81 and 81 GLUPS.
-constexpr int kStripNodes = 512;
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {
@@ -677,64 +673,19 @@ __device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0,
 }
 
 
-// Tile t of a lattice of tiles_x x tiles_y tiles, walked in vertical strips
-// of sw tile columns (the last strip narrower): within a strip row by row,
-// so the tile above was taken sw tiles earlier and its lines are still in
-// the L2 when this tile reads its halo.
-__device__ __forceinline__ void strip_tile(int t, int tiles_x, int tiles_y, int sw, int &tx, int &ty)
-{
-    const int full = tiles_x / sw, in_full = full * sw * tiles_y;
-    if (t < in_full) {
-        const int st = t / (sw * tiles_y), i = t - st * (sw * tiles_y);
-        ty = i / sw;
-        tx = st * sw + (i - ty * sw);
-    } else {
-        const int w = tiles_x - full * sw, i = t - in_full;
-        ty = i / w;
-        tx = full * sw + (i - ty * w);
-    }
-}
-
-// Division of 0 <= n < 2^31 by a fixed d >= 1 as a multiply and a shift
-// (Granlund and Montgomery's round-up method): with 2^(s-1) < d <= 2^s,
-// m = ceil(2^(31+s) / d) is below 2^32 and m d - 2^(31+s) < d <= 2^s, so
-// n m / 2^(31+s) exceeds n / d by less than 1/d and its floor is floor(n / d).
-// With n and the divisor uniform, the kernel does it on the scalar unit.
-struct FastDiv {
-    uint32_t m;
-    int32_t sh;
-};
-inline FastDiv fast_div(uint32_t d)
-{
-    int s = 0;
-    while (s < 31 && (1u << s) < d) ++s;
-    const uint64_t p = (uint64_t)1 << (31 + s);
-    return FastDiv{(uint32_t)((p + d - 1) / d), 31 + s};
-}
+// n / d for 0 <= n < 2^31 with d's multiply-and-shift constants (FastDiv);
+// with n and the constants uniform, on the scalar unit.
 __device__ __forceinline__ int div_by(int n, FastDiv f)
 {
     return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
 }
 
-// The strip walk of one lattice's tiles with its divisions prepared on the
-// host (strip_tile's arithmetic without integer divides in the kernel).
-struct StripWalk {
-    int32_t sw, tiles_y, full, in_full, w;  // strip width, tile rows, full strips, their tiles, last strip's width
-    FastDiv by_strip, by_sw, by_w;          // by sw * tiles_y, sw and w
-};
-inline StripWalk strip_walk(int tiles_x, int tiles_y, int sw)
-{
-    StripWalk p;
-    p.sw = sw;
-    p.tiles_y = tiles_y;
-    p.full = tiles_x / sw;
-    p.in_full = p.full * sw * tiles_y;
-    p.w = tiles_x - p.full * sw;
-    p.by_strip = fast_div((uint32_t)(sw * tiles_y));
-    p.by_sw = fast_div((uint32_t)sw);
-    p.by_w = fast_div((uint32_t)(p.w > 0 ? p.w : 1));
-    return p;
-}
+// Tile t (tx, ty) of a lattice of tiles_x x tiles_y tiles, walked in
+// vertical strips of sw tile columns (the last strip, of w columns,
+// narrower): within a strip row by row, so the tile above was taken sw
+// tiles earlier and its lines are still in the L2 when this tile reads its
+// halo.  The divisions by sw tiles_y, sw and w come prepared from the host
+// (StripWalk).
 __device__ __forceinline__ void strip_tile(int t, const StripWalk &p, int &tx, int &ty)
 {
     if (t < p.in_full) {
@@ -798,10 +749,8 @@ template <int ST, int FM, int SCH, typename I, typename TL>
 __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair, PairLds<ST, I, TL> &lds)
 {
     const int left = d.steps - 2 * pair;
-    const int tiles_x = (d.nx + TL::TW - 1) / TL::TW, tiles_y = (d.ny + TL::TH - 1) / TL::TH;
     int tx, ty;
-    constexpr int kSw = kStripNodes / TL::TW;
-    strip_tile((int)lt, tiles_x, tiles_y, tiles_x < kSw ? tiles_x : kSw, tx, ty);
+    strip_tile((int)lt, d.walk, tx, ty);
     const int x0 = tx * TL::TW, y0 = ty * TL::TH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
