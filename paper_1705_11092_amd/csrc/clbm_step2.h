@@ -479,12 +479,14 @@ __device__ __forceinline__ void to_storage(const typename Storage<ST>::R (&g)[9]
 // one tile row in both: phase A collides them (pulled as the one-step
 // kernel pulls them, slot 0 kept in registers) and then one node of the
 // region's ring, so LDS holds 8 slots and no tables.  It issues fewer
-// instructions per node update, which pays where VALU issue binds, the
+// instructions per node update, which pays most where VALU issue binds, the
 // 16-bit storage types (FP16 4096^2 191 -> 203 GLUPS, FP16-SR 170 -> 183,
-// BF16-SR 170 -> 187, their 256-lattice batches +17 %), and loses where it
-// does not (FP32 155 -> 152, FP64 84 -> 81, the FP32 batch 131 -> 126).  A tile at a
-// lattice's right edge (PACK) packs the threads onto the columns that lie
-// in the lattice, so that whole waves idle instead of every wave in part.
+// BF16-SR 170 -> 187, their 256-lattice batches +17 %); once its address
+// arithmetic lost its per-slot multiplies and divisions, one FP32 or FP64
+// lattice gained too (FP32 4096^2 155.7 -> 157.7, FP64 84.2 -> 84.9), while
+// batches of small FP32 lattices still lose (see kOwnNodesInBatch).  A tile
+// at a lattice's right edge (PACK) packs the threads onto the columns that
+// lie in the lattice, so that whole waves idle instead of every wave in part.
 template <int ST, int FM, int SCH, typename I, typename TL, bool PACK = false>
 __device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0, int y0,
                                               typename Storage<ST>::T (&lds)[8][TL::TH][TL::TW])
@@ -699,11 +701,19 @@ __device__ __forceinline__ void strip_tile(int t, const StripWalk &p, int &tx, i
     }
 }
 
-// The LDS of a pair tile: 9 slots and the coordinate tables (pair_tile),
-// or, for 16-bit storage, 8 slots (pair_tile_own).
+// The two forms of a pair tile: the region form (pair_tile) or the form in
+// which each thread collides its own nodes in both steps (pair_tile_own).
+// One lattice takes the own-node form for every storage type; batches take
+// it for 16-bit storage and keep the region form for FP32 and FP64, whose
+// batches of small lattices ran slower in the own-node form (4096 lattices
+// of 40^2 FP32: 116 against 108 GLUPS, 1024 of 100^2: 111 against 106; one
+// 4096^2 lattice: FP32 155.7 against 157.7, FP64 84.2 against 84.9).
 template <int ST>
-constexpr bool kOwnNodes = ST == ST_F16 || ST == ST_BF16 || ST == ST_F16_SR || ST == ST_BF16_SR;
-template <int ST, typename I, typename TL, bool OWN = kOwnNodes<ST>>
+constexpr bool kOwnNodesInBatch = ST == ST_F16 || ST == ST_BF16 || ST == ST_F16_SR || ST == ST_BF16_SR;
+
+// The LDS of a pair tile: 9 slots and the coordinate tables (region form),
+// or 8 slots (own-node form).
+template <int ST, typename I, typename TL, bool OWN>
 struct PairLds {
     alignas(16) typename Storage<ST>::T v[9][TL::TH][TL::TW];
     TileTabs<I, TL> tab;
@@ -717,10 +727,10 @@ struct PairLds<ST, I, TL, true> {
     alignas(16) typename Storage<ST>::T v[8][TL::TH][TL::TW];
 };
 
-template <int ST, int FM, int SCH, typename I, typename TL, bool PACK>
-__device__ __forceinline__ void pair_step(const LatDesc &d, int src, int x0, int y0, PairLds<ST, I, TL> &m)
+template <int ST, int FM, int SCH, typename I, typename TL, bool PACK, bool OWN>
+__device__ __forceinline__ void pair_step(const LatDesc &d, int src, int x0, int y0, PairLds<ST, I, TL, OWN> &m)
 {
-    if constexpr (kOwnNodes<ST>)
+    if constexpr (OWN)
         pair_tile_own<ST, FM, SCH, I, TL, PACK>(d, src, x0, y0, m.v);
     else
         pair_tile<ST, FM, SCH, I, TL, PACK>(d, src, x0, y0, m.v, m.tab);
@@ -729,7 +739,7 @@ __device__ __forceinline__ void pair_step(const LatDesc &d, int src, int x0, int
 template <int ST, int FM, int SCH, typename I, typename TL>
 __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, StripWalk sw)
 {
-    __shared__ PairLds<ST, I, TL> lds;
+    __shared__ PairLds<ST, I, TL, true> lds;
     // xcd_order gives each XCD a contiguous range of tile numbers, and the
     // strip walk puts a tile's left neighbour one tile and the one above it
     // sw tiles earlier in that range, so the halo lines a tile shares with
@@ -737,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, StripWalk 
     const int t = (int)xcd_order(blockIdx.x, gridDim.x);
     int tx, ty;
     strip_tile(t, sw, tx, ty);
-    pair_step<ST, FM, SCH, I, TL, false>(d, src, tx * TL::TW, ty * TL::TH, lds);
+    pair_step<ST, FM, SCH, I, TL, false, true>(d, src, tx * TL::TW, ty * TL::TH, lds);
 }
 
 // Tile lt of lattice d in batch pair substep `pair`: a lattice with at least
@@ -746,7 +756,8 @@ __global__ __launch_bounds__(kBlock) void k_step2(LatDesc d, int src, StripWalk 
 // be odd).  The buffer parity of these lattices counts launches: pair p
 // reads buffer parity + p.  Within a lattice the tiles take the strip walk.
 template <int ST, int FM, int SCH, typename I, typename TL>
-__device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair, PairLds<ST, I, TL> &lds)
+__device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, int pair,
+                                                PairLds<ST, I, TL, kOwnNodesInBatch<ST>> &lds)
 {
     const int left = d.steps - 2 * pair;
     int tx, ty;
@@ -754,7 +765,7 @@ __device__ __forceinline__ void batch_pair_tile(const LatDesc &d, int64_t lt, in
     const int x0 = tx * TL::TW, y0 = ty * TL::TH;
     const int src = (d.parity + pair) & 1;
     if (left >= 2) {
-        pair_step<ST, FM, SCH, I, TL, true>(d, src, x0, y0, lds);
+        pair_step<ST, FM, SCH, I, TL, true, kOwnNodesInBatch<ST>>(d, src, x0, y0, lds);
     } else {
         // The one-step node update in groups of 4 (TW / 4 threads per tile
         // row; with 2 nodes per thread in phase B only half the threads).
@@ -772,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2(const LatDesc *__restrict__ l
                                                    const int32_t *__restrict__ tile_lat, int64_t ntiles,
                                                    int pair)
 {
-    __shared__ PairLds<ST, I, TL> lds;
+    __shared__ PairLds<ST, I, TL, kOwnNodesInBatch<ST>> lds;
     const int64_t t = xcd_order(blockIdx.x, ntiles);
     const LatDesc &d = lats[tile_lat[t]];
     if (d.steps - 2 * pair <= 0) return;  // the whole block: one lattice per tile
@@ -788,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2p(const LatDesc *__restrict__ 
                                                     const int32_t *__restrict__ tile_lat, int64_t ntiles,
                                                     int pair)
 {
-    __shared__ PairLds<ST, I, TL> lds;
+    __shared__ PairLds<ST, I, TL, kOwnNodesInBatch<ST>> lds;
     const int64_t G = gridDim.x;
     const int64_t b = xcd_order(blockIdx.x, G);
     const int64_t lo = b * ntiles / G, hi = (b + 1) * ntiles / G;
