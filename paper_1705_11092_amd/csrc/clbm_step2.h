@@ -677,7 +677,7 @@ __device__ __forceinline__ void pair_tile_own(const LatDesc &d, int src, int x0,
 
 // n / d for 0 <= n < 2^31 with d's multiply-and-shift constants (FastDiv);
 // with n and the constants uniform, on the scalar unit.
-__device__ __forceinline__ int div_by(int n, FastDiv f)
+__host__ __device__ __forceinline__ int div_by(int n, FastDiv f)
 {
     return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
 }
@@ -688,7 +688,7 @@ __device__ __forceinline__ int div_by(int n, FastDiv f)
 // tiles earlier and its lines are still in the L2 when this tile reads its
 // halo.  The divisions by sw tiles_y, sw and w come prepared from the host
 // (StripWalk).
-__device__ __forceinline__ void strip_tile(int t, const StripWalk &p, int &tx, int &ty)
+__host__ __device__ __forceinline__ void strip_tile(int t, const StripWalk &p, int &tx, int &ty)
 {
     if (t < p.in_full) {
         const int st = div_by(t, p.by_strip), i = t - st * (p.sw * p.tiles_y);

@@ -12,13 +12,21 @@ restate that arithmetic and check that the walk visits every tile once,
 that every LDS entry phase B reads is written exactly once, by the source
 the pull with half-way bounce-back names, that the region row of a region
 node comes out exact from its float product, that the multiply-and-shift
-divisions of the single-lattice walk equal integer division, and that
+divisions of the walk equal integer division (restated, and the kernels'
+own code built for the host from tests/host_walk.hip), and that
 phase B's stores cover each row and its padding up to the next multiple of
 4 exactly once.
 """
+import ctypes
+import os
 import random
+import subprocess
 
+import numpy as np
 import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
@@ -80,6 +88,58 @@ def test_fast_division_is_exact_below_2_31():
         for n in ns:
             if 0 <= n < 1 << 31:
                 assert div_by(n, f) == n // d, (d, n)
+
+
+@pytest.fixture(scope="module")
+def walk_lib(tmp_path_factory):
+    """tests/host_walk.hip: the kernels' strip walk and divisions built for the host."""
+    out = tmp_path_factory.mktemp("host_walk") / "libhost_walk.so"
+    subprocess.check_call([HIPCC, "--offload-host-only", "-O2", "-std=c++17", "-fPIC", "-shared",
+                           "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_1705_11092_amd", "csrc"),
+                           "-o", str(out), os.path.join(ROOT, "tests", "host_walk.hip")],
+                          stderr=subprocess.DEVNULL)
+    h = ctypes.CDLL(str(out))
+    h.host_div_by.argtypes = [ctypes.c_uint32, ctypes.c_int]
+    h.host_div_by.restype = ctypes.c_int
+    ip = ctypes.POINTER(ctypes.c_int)
+    h.host_strip_walk.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, ip, ip]
+    return h
+
+
+def test_kernel_division_is_exact_below_2_31(walk_lib):
+    """The kernels' own multiply-and-shift division, compiled for the host."""
+    rng = random.Random(11)
+    divisors = list(range(1, 600)) + [(1 << k) + o for k in range(10, 31) for o in (-1, 0, 1)]
+    divisors += [rng.randrange(1, 1 << 31) for _ in range(100)] + [(1 << 31) - 1]
+    for d in divisors:
+        ns = {0, 1, d - 1, d, d + 1, (1 << 31) - 1, (1 << 31) - 1 - d}
+        ns |= {rng.randrange(0, 1 << 31) for _ in range(10)}
+        ns |= {q * d + r for q in (1, 3, (1 << 31) // d - 1) for r in (0, d - 1)}
+        for n in ns:
+            if 0 <= n < 1 << 31:
+                assert walk_lib.host_div_by(d, n) == n // d, (d, n)
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+@pytest.mark.parametrize("nx,ny", [(1, 1), (65, 17), (300, 70), (1030, 9), (4096, 4096), (520, 200),
+                                   (32768, 32768)])
+def test_kernel_strip_walk_names_the_strip_walk_tile(walk_lib, nx, ny, tw, th):
+    """The kernels' prepared walk, compiled for the host, against strip_tile."""
+    tiles_x, tiles_y = (nx + tw - 1) // tw, (ny + th - 1) // th
+    sw = min(tiles_x, STRIP_NODES // tw)
+    n = tiles_x * tiles_y
+    full = tiles_x // sw
+    in_full = full * sw * tiles_y
+    ts = range(n) if n <= 20000 else sorted(t for t in {0, n - 1, in_full - 1, in_full} | set(range(0, n, 997)) if 0 <= t < n)
+    t = np.ascontiguousarray(np.array(list(ts), dtype=np.int32))
+    tx = np.zeros_like(t)
+    ty = np.zeros_like(t)
+    ip = ctypes.POINTER(ctypes.c_int)
+    walk_lib.host_strip_walk(tiles_x, tiles_y, sw, t.ctypes.data_as(ip), len(t), tx.ctypes.data_as(ip),
+                             ty.ctypes.data_as(ip))
+    for k in range(len(t)):
+        assert (int(tx[k]), int(ty[k])) == strip_tile(int(t[k]), tiles_x, tiles_y, sw), (int(t[k]), nx, ny)
 
 
 @pytest.mark.parametrize("tw,th", SHAPES)
