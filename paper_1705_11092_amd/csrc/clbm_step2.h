@@ -824,7 +824,8 @@ hipError_t launch_step2_st(const LatDesc &d, int src, hipStream_t s)
     // FP64: 64 x 8 tiles with 2 nodes per thread in phase B.  Their 37 KB
     // of LDS let four blocks share a compute unit where the 74 KB of a
     // 64 x 16 tile let two: 4096^2 went from 70 to 84 GLUPS (32 x 16 tiles:
-    // 81), though they collide more halo (66 x 10 region nodes per 512).
+    // 81; in the own-node form 79.7 against 85.1), though they collide more
+    // halo (66 x 10 region nodes per 512).
     // FP32 and 16-bit storage keep 64 x 16 (with 32 x 16 FP32 lost 3 %, FP16
     // 13 %).
     using TL = std::conditional_t<ST == ST_F64, T64x8, T64x16>;
