@@ -20,6 +20,14 @@
 // lies beyond a wall, the node's own post-collision slot opp(i) (half-way
 // bounce-back), which phase A writes there in place of the absent node.
 // Phase B thus reads NPT consecutive nodes of a slot as one aligned vector.
+//
+// Two forms do phase A: the region form (pair_tile) spreads the region's
+// nodes over the threads through per-tile coordinate tables; the own-node
+// form (pair_tile_own) lets each thread collide in phase A the very nodes it
+// collides in phase B, keeps their slot 0 in registers (8 LDS slots) and
+// gives each thread at most one node of the region's ring.  One lattice
+// takes the own-node form; batches take it for 16-bit storage
+// (kOwnNodesInBatch).
 #pragma once
 
 #include <type_traits>
